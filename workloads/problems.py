@@ -1,0 +1,273 @@
+"""Seeded synthetic workloads: grids, parameters, boundary edges, initial fields.
+
+A workload is a plain dict (no arithmetic of the lattice Boltzmann method is
+done here); the CPU oracle and the GPU binding each turn it into their own
+parameter structures. Keys:
+
+  nx, ny          interior sites; site (i, j) has centre ((i+.5)dx, (j+.5)dx)
+  dx, dt          grid spacing (dx = dy, Sec. 3 before Eq. (SEC-VON-13)) and time step
+  c1, c2, eta0    KT velocity-set constants, Eqs. (e14)-(e15)
+  gamma           specific-heat ratio, b = 2/(gamma-1)
+  tau             relaxation time in units of dt (the paper fixes dt = Knudsen number)
+  beta            upwind mixing of Eqs. (SEC-VON-2a/2b)
+  lam             None for the paper's rule Eq. (SEC-VON-13), else 9 explicit values
+  lam0_scale      multiplier on lambda_0 when lam is None (Fig. 9b sweep)
+  edges           [x-, x+, y-, y+] edge dicts:
+                    {"kind": "periodic"|"outflow"|"wall"|"inflow"|"shock",
+                     "split": k, "a": state, "b": state, "x0":, "angle_deg":, "speed":}
+                  "split" k > 0 makes the first k cells along the edge inflow of
+                  state "a" (the double-Mach-reflection bottom edge ahead of the wall);
+                  "shock": ghost cells with x < x0 + y/tan(angle) + speed*t/sin(angle)
+                  take state "a", the others state "b" (moving oblique shock).
+  steps           number of time steps of the workload
+States are (rho, ux, uy, p) tuples.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import gasdyn
+
+GAMMA = 1.4
+
+
+def _edge(kind, **kw):
+    d = {"kind": kind, "split": 0, "a": (1.0, 0.0, 0.0, 1.0), "b": (1.0, 0.0, 0.0, 1.0),
+         "x0": 0.0, "angle_deg": 90.0, "speed": 0.0}
+    d.update(kw)
+    return d
+
+
+def _base(nx, ny, dx, dt, c1, c2, eta0, steps, edges, **kw):
+    d = {"nx": nx, "ny": ny, "dx": dx, "dt": dt, "c1": c1, "c2": c2, "eta0": eta0,
+         "gamma": GAMMA, "tau": 1.0, "beta": 0.25, "lam": None, "lam0_scale": 1.0,
+         "edges": edges, "steps": steps}
+    d.update(kw)
+    return d
+
+
+def riemann_edges():
+    """Zero-gradient x ends, periodic y: a 1D Riemann problem on a 2D grid."""
+    return [_edge("outflow"), _edge("outflow"), _edge("periodic"), _edge("periodic")]
+
+
+def riemann_fields(cfg, left, right, x_disc):
+    """(rho, ux, uy, p) arrays of shape (ny, nx): left state for x < x_disc."""
+    nx, ny, dx = cfg["nx"], cfg["ny"], cfg["dx"]
+    x = (np.arange(nx) + 0.5) * dx
+    out = []
+    for k in range(4):
+        row = np.where(x < x_disc, left[k], right[k]).astype(np.float64)
+        out.append(np.ascontiguousarray(np.broadcast_to(row, (ny, nx))))
+    return tuple(out)
+
+
+# ------------------------------------------------------------------ configurations
+
+def sod(nx=200, ny=4, steps=500):
+    """Sod shock tube: (1,0,0,1) | (0.125,0,0,0.1) on [0,1]; c1,c2,eta0 = 1,3,2."""
+    dx = 1.0 / nx
+    cfg = _base(nx, ny, dx, 0.08 * dx, 1.0, 3.0, 2.0, steps, riemann_edges(), name="sod")
+    cfg["left"], cfg["right"], cfg["x_disc"] = (1.0, 0.0, 0.0, 1.0), (0.125, 0.0, 0.0, 0.1), 0.5
+    return cfg
+
+
+def ratio1000(nx=2000, ny=4, steps=4000):
+    """1000:1 Riemann problem, Eq. (Riemann-2); dx = 0.0025, c1,c2,eta0 = 3,9,5.
+
+    dt = 0.072 dx/c2 = 2e-5 (the printed 2e-4 is not stable, see the design notes)."""
+    dx = 0.0025
+    cfg = _base(nx, ny, dx, 2e-5, 3.0, 9.0, 5.0, steps, riemann_edges(), name="ratio1000")
+    cfg["left"], cfg["right"], cfg["x_disc"] = (1000.0, 0.0, 0.0, 1000.0), (1.0, 0.0, 0.0, 1.0), 0.5 * nx * dx
+    return cfg
+
+
+def mach30(nx=1200, ny=4, steps=None, alpha=0.05, beta=0.25, lam0_scale=1.0):
+    """Mach-30 Riemann problem, Eq. (Riemann-1); dx = 0.01, c1,c2,eta0 = 25,50,30."""
+    dx = 0.01
+    dt = alpha * dx / 50.0
+    if steps is None:
+        steps = int(round(0.36 / dt))
+    cfg = _base(nx, ny, dx, dt, 25.0, 50.0, 30.0, steps, riemann_edges(), name="mach30",
+                beta=beta, lam0_scale=lam0_scale)
+    cfg["left"], cfg["right"], cfg["x_disc"] = (1.4, 30.0, 0.0, 1.0), (1.4, 0.0, 0.0, 1.0), 0.25 * nx * dx
+    return cfg
+
+
+def init_riemann(cfg):
+    return riemann_fields(cfg, cfg["left"], cfg["right"], cfg["x_disc"])
+
+
+def regular_reflection(nx=300, ny=90, steps=20000, mach=2.9, wave_angle_deg=30.0, seed=0):
+    """Regular reflection of an oblique shock off the bottom wall (Sec. 4.2).
+
+    Left: inflow (1, mach, 0, 1/gamma) (sound speed 1); top: the state behind a
+    `wave_angle_deg` oblique shock of that inflow; bottom: reflecting wall;
+    right: supersonic outflow. c1,c2,eta0 = 3,9,5; dt = 0.2 dx/c2.
+    """
+    dx = 0.01
+    inflow = (1.0, mach, 0.0, 1.0 / GAMMA)
+    top = gasdyn.oblique_shock_state(GAMMA, inflow, wave_angle_deg)
+    edges = [_edge("inflow", a=inflow), _edge("outflow"), _edge("wall"), _edge("inflow", a=top)]
+    cfg = _base(nx, ny, dx, 0.2 * dx / 9.0, 3.0, 9.0, 5.0, steps, edges, name="regular_reflection")
+    cfg["inflow"], cfg["top"], cfg["seed"] = inflow, top, seed
+    cfg["wave_angle_deg"] = wave_angle_deg
+    return cfg
+
+
+def init_regular_reflection(cfg):
+    """Inflow state everywhere (Sec. 4.2), density times (1 + U[-1e-6, 1e-6])."""
+    nx, ny = cfg["nx"], cfg["ny"]
+    rng = np.random.default_rng(cfg["seed"])
+    xi = rng.uniform(-1e-6, 1e-6, size=(ny, nx))
+    r, u, v, p = cfg["inflow"]
+    return (r * (1.0 + xi), np.full((ny, nx), u), np.full((ny, nx), v), np.full((ny, nx), p))
+
+
+def double_mach(nx=960, ny=240, steps=2000, length=9.6, wall_cells=None):
+    """Double Mach reflection (Sec. 4.2, Fig. 12): Mach-10 shock at 60 deg to the wall.
+
+    Pre-shock (1.4, 0, 0, 1); post-shock from the normal-shock relations; the
+    wall starts `wall_cells` cells from the lower-left corner (20 at dx = 0.01,
+    the same physical offset 0.2 at other resolutions); c1,c2,eta0 = 8,16,10;
+    dt = 0.1 dx/c2.
+    """
+    dx = length / nx
+    x0 = 0.2 if wall_cells is None else wall_cells * dx
+    split = int(round(x0 / dx))
+    pre = (1.4, 0.0, 0.0, 1.0)
+    post = gasdyn.moving_shock_post_state(GAMMA, (1.4, 1.0), 10.0, -30.0)
+    edges = [_edge("inflow", a=post), _edge("outflow"),
+             _edge("wall", split=split, a=post),
+             _edge("shock", a=post, b=pre, x0=x0, angle_deg=60.0, speed=10.0)]
+    cfg = _base(nx, ny, dx, 0.1 * dx / 16.0, 8.0, 16.0, 10.0, steps, edges, name="double_mach")
+    cfg["pre"], cfg["post"], cfg["x0"] = pre, post, x0
+    return cfg
+
+
+def init_double_mach(cfg):
+    nx, ny, dx = cfg["nx"], cfg["ny"], cfg["dx"]
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dx
+    X, Y = np.meshgrid(x, y)
+    behind = X < cfg["x0"] + Y / math.tan(math.radians(60.0))
+    out = []
+    for k in range(4):
+        out.append(np.where(behind, cfg["post"][k], cfg["pre"][k]).astype(np.float64))
+    return tuple(out)
+
+
+def roofline_grid(nx=8192, ny=2048):
+    """The double-Mach-reflection field on a grid too large for the on-chip caches."""
+    cfg = double_mach(nx=nx, ny=ny, length=9.6)
+    cfg["workload"] = "double-Mach-reflection field on %dx%d" % (nx, ny)
+    return cfg
+
+
+def dmr_target_density(cfg, rho0, seed=1):
+    """Target initial density: pre-shock sites times (1 + 0.01 U[-1,1])."""
+    rng = np.random.default_rng(seed)
+    xi = rng.uniform(-1.0, 1.0, size=rho0.shape)
+    pre = np.isclose(rho0, cfg["pre"][0])
+    return np.where(pre, rho0 * (1.0 + 0.01 * xi), rho0)
+
+
+def init_fields(cfg):
+    name = cfg["name"]
+    if name in ("sod", "ratio1000", "mach30", "batched"):
+        return init_riemann(cfg)
+    if name == "regular_reflection":
+        return init_regular_reflection(cfg)
+    if name == "double_mach":
+        return init_double_mach(cfg)
+    if name == "periodic_smooth":
+        return init_periodic_smooth(cfg)
+    raise KeyError(name)
+
+
+# ------------------------------------------------------------------ generic test fields
+
+def periodic_smooth(nx=24, ny=16, steps=10, seed=3, c=(3.0, 9.0, 5.0), alpha=0.1):
+    """Fully periodic grid with a smooth random field (conservation tests)."""
+    dx = 0.01
+    edges = [_edge("periodic") for _ in range(4)]
+    cfg = _base(nx, ny, dx, alpha * dx / c[1], c[0], c[1], c[2], steps, edges, name="periodic_smooth")
+    cfg["seed"] = seed
+    return cfg
+
+
+def init_periodic_smooth(cfg):
+    """Low Fourier modes with seeded amplitudes and phases; rho, p stay positive."""
+    nx, ny = cfg["nx"], cfg["ny"]
+    rng = np.random.default_rng(cfg["seed"])
+    x = np.arange(nx) / nx
+    y = np.arange(ny) / ny
+    X, Y = np.meshgrid(x, y)
+    fields = []
+    base = [1.0, 0.5, -0.3, 1.0]
+    amp = [0.2, 0.3, 0.3, 0.2]
+    for k in range(4):
+        acc = np.full((ny, nx), base[k])
+        for (kx, ky) in ((1, 0), (0, 1), (1, 1), (2, 1)):
+            a = rng.uniform(-1, 1) * amp[k] / 2
+            ph = rng.uniform(0, 2 * math.pi)
+            acc = acc + a * np.cos(2 * math.pi * (kx * X + ky * Y) + ph)
+        fields.append(acc)
+    return tuple(fields)
+
+
+def random_distributions(nx, ny, seed, lo=0.5, hi=1.5):
+    """A raw (9, ny, nx) array of positive values: a non-equilibrium input state."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(9, ny, nx))
+
+
+# ------------------------------------------------------------------ batched draws
+
+def batched(nprob=256, seed=0, steps=2000, alpha=0.025, lmin=128, lmax=8192, ny=4):
+    """Independent 1D Riemann problems of uneven lengths (log-uniform in [lmin, lmax]).
+
+    Per problem: rho and p log-uniform in [0.1, 1000] per side with max/min <= 1000;
+    |u| = M c_side with M ~ U[0, 5] (every 8th problem: U[5, 30]) and a random sign;
+    draws that create vacuum are rejected and counted. c1 = U + 3 sqrt(T_max) over
+    both sides and the exact star states, c2 = 2 c1, eta0 = 1.5 c1,
+    dt = alpha dx / c2, dx = 1/L.
+    Returns (list of cfg dicts, number of vacuum rejections).
+    """
+    rng = np.random.default_rng(seed)
+    out, rejected = [], 0
+    for p_idx in range(nprob):
+        L = int(round(math.exp(rng.uniform(math.log(lmin), math.log(lmax)))))
+        fast = (p_idx % 8 == 7)
+        while True:
+            while True:
+                rho = np.exp(rng.uniform(math.log(0.1), math.log(1000.0), size=2))
+                pr = np.exp(rng.uniform(math.log(0.1), math.log(1000.0), size=2))
+                if rho.max() / rho.min() <= 1000.0 and pr.max() / pr.min() <= 1000.0:
+                    break
+            cs = np.sqrt(GAMMA * pr / rho)
+            M = rng.uniform(5.0, 30.0, size=2) if fast else rng.uniform(0.0, 5.0, size=2)
+            sgn = np.where(rng.uniform(size=2) < 0.5, -1.0, 1.0)
+            u = sgn * M * cs
+            left = (float(rho[0]), float(u[0]), float(pr[0]))
+            right = (float(rho[1]), float(u[1]), float(pr[1]))
+            try:
+                st = gasdyn.riemann_star(GAMMA, left, right)
+            except ValueError:
+                rejected += 1
+                continue
+            break
+        U = max(abs(left[1]), abs(right[1]), abs(st.u))
+        Tmax = max(left[2] / left[0], right[2] / right[0], st.p / st.rho_l, st.p / st.rho_r)
+        c1 = U + 3.0 * math.sqrt(Tmax)
+        c2, eta0 = 2.0 * c1, 1.5 * c1
+        dx = 1.0 / L
+        cfg = _base(L, ny, dx, alpha * dx / c2, c1, c2, eta0, steps, riemann_edges(), name="batched")
+        cfg["left"] = (left[0], left[1], 0.0, left[2])
+        cfg["right"] = (right[0], right[1], 0.0, right[2])
+        cfg["x_disc"] = 0.5
+        cfg["fast"] = fast
+        out.append(cfg)
+    return out, rejected
