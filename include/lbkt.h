@@ -1,0 +1,211 @@
+/*
+ * lbkt.h - C ABI of the MI355X (gfx950) finite-difference lattice Boltzmann step.
+ *
+ * Method: Pan, Xu, Zhang & Jiang, "Lattice Boltzmann approach to high-speed
+ * compressible flows" (2007). One time step of the Kataoka-Tsutahara D2V9
+ * discrete-velocity model (Sec. 2, Eqs. (e14)-(e18)) advanced by the forward
+ * Euler / beta-mixed upwind finite-difference scheme (Eqs. (SEC-VON-1),
+ * (SEC-VON-2a/2b)) with the added dissipation term lambda_i Laplacian(f_i)
+ * (Eqs. (SEC-VON-11), (SEC-VON-13)):
+ *
+ *   f_i' = f_i - dt v_ia D_a f_i + dt lambda_i (d2/dx2 + d2/dy2) f_i + (f_i^eq - f_i)/tau
+ *
+ * with rho, u, T from Eqs. (e4), (e5), (e7) (R = 1, b = 2/(gamma-1)) and f^eq
+ * from Eq. (e16). tau is in units of dt (the paper sets dt equal to the Knudsen
+ * number). dx is used for both axes (the paper takes dx = dy).
+ *
+ * Data layout ("SoA planes"): a distribution array holds 9 planes, plane i in
+ * the velocity order of Eq. (e14):
+ *     0:(0,0) 1:(-c1,0) 2:(0,-c1) 3:(c1,0) 4:(0,c1)
+ *     5:(-s,-s) 6:(s,-s) 7:(s,s) 8:(-s,s),   s = c2/sqrt(2)
+ * Element (i, y, x) is at  f[i*pitch*ny + y*pitch + x]  (x fastest, pitch >= nx,
+ * pitch a multiple of 64 elements, base pointer 256-byte aligned). Site (x, y)
+ * has centre ((x+0.5) dx, (y+0.5) dx). Macroscopic fields (rho, ux, uy, p or T)
+ * are dense row-major (ny, nx) float64 arrays.
+ *
+ * Precision: LB_F64 stores f in float64; LB_F32 stores f in float32 and widens
+ * every load to float64, so moments, the division by rho, T, f^eq and the
+ * stencil run in float64 and only the store rounds to float32. Adjoint fields
+ * are always float64.
+ *
+ * Boundaries: one ghost cell per edge (the stencil is a 5-point cross, corners
+ * are never read), edge order x-, x+, y-, y+:
+ *   LB_BC_PERIODIC  wrap (both edges of an axis must be periodic)
+ *   LB_BC_OUTFLOW   zero gradient: the ghost copies the adjacent interior cell
+ *   LB_BC_WALL      reflecting wall on the cell face: ghost = adjacent interior
+ *                   cell with the velocity planes mirrored across the wall
+ *   LB_BC_INFLOW    Dirichlet: ghost = f^eq of state a
+ *   LB_BC_SHOCK     (y edges only) ghost = f^eq(a) where its centre x lies behind
+ *                   x_s = x0 + y/tan(angle) + speed t / sin(angle), t = step*dt,
+ *                   and f^eq(b) elsewhere (a moving straight shock)
+ *   split > 0       the first `split` ghost cells along the edge use f^eq(a)
+ *                   whatever the kind (a wall that starts downstream).
+ *
+ * Conventions of every call:
+ *   - All device pointers are caller-allocated (e.g. by PyTorch); the library
+ *     never frees caller memory and returns no caller-visible allocation.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Calls
+ *     are asynchronous on that stream unless stated otherwise.
+ *   - Parameter, size and alias errors are detected on the host before any
+ *     launch and return a negative lb_status; lb_last_error() gives detail
+ *     text (thread-local). HIP errors map to LB_EHIP.
+ *   - Numerical blow-up is reported through lb_moments' flags.
+ */
+#ifndef LBKT_H
+#define LBKT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LB_OK = 0,
+  LB_EINVAL = -1,      /* null pointer, bad size, pitch or alignment */
+  LB_EPARAM = -2,      /* c1 == c2, c1,c2,eta0,dx,dt,tau <= 0, beta outside [0,0.5], gamma <= 1, lambda < 0 */
+  LB_EALIAS = -3,      /* input and output arrays overlap */
+  LB_ENONFINITE = -4,  /* reserved for callers that turn flags into a status */
+  LB_EHIP = -5,        /* a HIP runtime call failed */
+  LB_ENOMEM = -6,      /* internal metadata allocation failed */
+  LB_EUNSUPPORTED = -7 /* valid request the library does not implement */
+} lb_status;
+
+typedef enum { LB_F64 = 0, LB_F32 = 1 } lb_prec;
+
+typedef enum {
+  LB_BC_PERIODIC = 0,
+  LB_BC_OUTFLOW = 1,
+  LB_BC_WALL = 2,
+  LB_BC_INFLOW = 3,
+  LB_BC_SHOCK = 4
+} lb_bc_kind;
+
+/* flags word bits written by lb_moments */
+enum { LB_FLAG_NONFINITE = 1u, LB_FLAG_RHO_NONPOS = 2u, LB_FLAG_T_NONPOS = 4u };
+
+typedef struct { double rho, ux, uy, p; } lb_state;
+
+typedef struct {
+  int32_t kind;        /* lb_bc_kind */
+  int32_t split;       /* first `split` ghost cells along the edge are f^eq(a) */
+  lb_state a, b;       /* INFLOW: a; SHOCK: a behind, b ahead */
+  double x0, angle_deg, speed; /* SHOCK geometry */
+} lb_edge;
+
+typedef struct {
+  int32_t nx, ny;      /* interior sites */
+  int64_t pitch;       /* row pitch in elements (multiple of 64, >= nx) */
+  double dx, dt;       /* grid spacing (both axes) and time step */
+  double c1, c2, eta0; /* Eqs. (e14)-(e15) */
+  double gamma;        /* specific-heat ratio, b = 2/(gamma-1) */
+  double tau;          /* relaxation time in units of dt */
+  double beta;         /* upwind mixing of Eqs. (SEC-VON-2a/2b), 0 <= beta <= 0.5 */
+  double lambda[9];    /* dissipation coefficients lambda_i of Eq. (SEC-VON-11) */
+  lb_edge edge[4];     /* x-, x+, y-, y+ */
+} lb_grid;
+
+/* Launch shape of the step kernels: block_x threads per block (64, 128 or 256,
+ * one column each) and `rows` rows marched per block (>= 1). {0,0} = default. */
+typedef struct { int32_t block_x, rows; } lb_tile;
+
+/* Fill grid->lambda with Eq. (SEC-VON-13): c1 dx, c1 dx/10 (i = 1..4), 0 (i = 5..8). */
+lb_status lb_default_lambda(lb_grid* grid);
+
+/* Host-only validation of every field of *grid (no GPU needed). */
+lb_status lb_validate(const lb_grid* grid);
+
+/* Number of elements of one distribution array (9 * pitch * ny). */
+int64_t lb_array_elems(const lb_grid* grid);
+
+/* Initialisation (Sec. 4.2: the field starts at equilibrium): f := f^eq(rho, u, p/rho)
+ * from dense float64 device fields. f has the storage type of `prec`. */
+lb_status lb_init(const lb_grid* grid, lb_prec prec, const double* rho, const double* ux,
+                  const double* uy, const double* p, void* f, void* stream);
+
+/* One time step f_out = S(f_in) at time index `step` (t = step*dt, used by SHOCK
+ * edges). f_in and f_out must not overlap. */
+lb_status lb_step(const lb_grid* grid, lb_prec prec, const void* f_in, void* f_out, int64_t step,
+                  void* stream);
+
+/* lb_step with an explicit launch shape (tile NULL = default). Every tile gives
+ * bitwise the same result. */
+lb_status lb_step_tiled(const lb_grid* grid, lb_prec prec, const void* f_in, void* f_out,
+                        int64_t step, const lb_tile* tile, void* stream);
+
+/* nsteps ping-pong steps from f_a at time index step0. The result is in f_a when
+ * nsteps is even, else in f_b. use_graph != 0 captures the launches in a HIP graph
+ * (cached: a repeated call with the same arguments replays it). */
+lb_status lb_run(const lb_grid* grid, lb_prec prec, void* f_a, void* f_b, int64_t step0,
+                 int32_t nsteps, int32_t use_graph, const lb_tile* tile, void* stream);
+
+/* Moments of f (Eqs. (e4), (e5), (e7)) into dense float64 device fields (any of
+ * rho/ux/uy/T may be NULL), and, if flags != NULL, a device uint32[4]:
+ * flags[0] = OR of LB_FLAG_* over all sites, flags[1..3] = number of sites that are
+ * non-finite, have rho <= 0, have T <= 0. The flags array is cleared by the call. */
+lb_status lb_moments(const lb_grid* grid, lb_prec prec, const void* f, double* rho, double* ux,
+                     double* uy, double* T, uint32_t* flags, void* stream);
+
+/* Domain totals (sum over sites of rho, rho ux, rho uy, rho (b T + u^2)) into a
+ * device double[4]. Deterministic (fixed reduction order). Uses an internal
+ * per-device workspace allocated on first use. */
+lb_status lb_invariants(const lb_grid* grid, lb_prec prec, const void* f, double* out4,
+                        void* stream);
+
+/* Adjoint (vector-Jacobian product) of lb_step at f_n: g_n = (dS/df)^T g_np1.
+ * g_np1 and g_n are float64 arrays of the distribution layout; f_n has the
+ * storage type of `prec` (the float32 rounding of the store is treated as the
+ * identity). g_np1 and g_n must not overlap. The paper has no adjoint: this is
+ * the exact transpose of the step's linearisation (upwinding by the fixed sign
+ * of v, no limiter, so the step is smooth in f where rho != 0). */
+lb_status lb_step_adjoint(const lb_grid* grid, lb_prec prec, const void* f_n, const double* g_np1,
+                          double* g_n, int64_t step, void* stream);
+
+/* Adjoint of lb_init with respect to rho at fixed u and p:
+ * g_rho[x] = sum_i g_f0_i(x) d f_i^eq(rho, u, p/rho) / d rho. */
+lb_status lb_init_adjoint(const lb_grid* grid, const double* rho, const double* ux,
+                          const double* uy, const double* p, const double* g_f0, double* g_rho,
+                          void* stream);
+
+/* Batched independent problems (a batch of 1D/2D grids with their own
+ * parameters) stored back to back in one packed array. */
+typedef struct lb_batch lb_batch;
+
+/* Build a batch from a host array of grids (pitch fields are ignored and
+ * recomputed). Uploads per-problem constants and a work list. */
+lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, lb_prec prec, lb_batch** out);
+
+/* Element offset of each problem's array inside the packed array (host int64[nprob])
+ * and the total element count; each problem p is a normal distribution array with
+ * the pitch written to pitches[p] (host int64[nprob], may be NULL). */
+lb_status lb_batch_layout(const lb_batch* b, int64_t* offsets, int64_t* pitches, int64_t* total);
+
+/* Set the launch shape of the batched step (block_x threads per work item;
+ * rows is ignored: a work item covers all rows of its problem). */
+lb_status lb_batch_set_tile(lb_batch* b, const lb_tile* tile);
+
+/* nsteps steps of every problem, all problems per launch, the nsteps launches
+ * captured once in a HIP graph and replayed as one graph launch. Result in f_a
+ * when nsteps is even, else f_b. step index starts at 0 on the first call and
+ * continues across calls. */
+lb_status lb_step_batched(lb_batch* b, void* f_a, void* f_b, int32_t nsteps, void* stream);
+
+void lb_batch_destroy(lb_batch* b);
+
+/* Time each candidate launch shape for (grid, prec) with HIP events on `stream`
+ * (reps steps each) and return the fastest in *best; f_a/f_b are scratch state. */
+lb_status lb_autotune(const lb_grid* grid, lb_prec prec, void* f_a, void* f_b, int32_t reps,
+                      lb_tile* best, float* best_ms, void* stream);
+
+/* ABI self-description for bindings: sizeof(lb_grid) (which = 0), sizeof(lb_edge)
+ * (1), sizeof(lb_state) (2), sizeof(lb_tile) (3); -1 for other values. */
+int64_t lb_struct_size(int32_t which);
+
+const char* lb_status_str(lb_status s);
+const char* lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBKT_H */

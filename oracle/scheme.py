@@ -86,7 +86,8 @@ def feq_state(pb: Problem, state):
 
 def init(pb: Problem, rho, ux, uy, p):
     """f^0 = f_eq(rho, u, p/rho) from (ny, nx) fields."""
-    rho, ux, uy, p = (torch.tensor(np.array(a, dtype=np.float64)) for a in (rho, ux, uy, p))
+    rho, ux, uy, p = (a.to(F64) if isinstance(a, torch.Tensor) else torch.tensor(np.array(a, dtype=np.float64))
+                      for a in (rho, ux, uy, p))
     return kt.feq(rho, ux, uy, p / rho, pb.c1, pb.c2, pb.eta0, pb.gamma)
 
 
@@ -151,13 +152,19 @@ def upwind_derivative(fp, f0, fm, v, beta, dx):
 
 def step(pb: Problem, f, n: int = 0):
     """f^{n+1} from f^n (shape (9, ny, nx)); n sets t = n dt for moving-shock edges."""
+    return step_rows(pb, f, n, None)
+
+
+def step_rows(pb: Problem, f, n: int, rows):
+    """Rows `rows` (a list of y indices, None = all) of f^{n+1}; shape (9, len(rows), nx)."""
     F = pad(pb, f, n * pb.dt)
+    r = torch.arange(pb.ny) if rows is None else torch.as_tensor(rows, dtype=torch.long)
     v = kt.velocities(pb.c1, pb.c2)
-    rho, ux, uy, T = kt.moments(f, pb.c1, pb.c2, pb.eta0, pb.gamma)
+    rho, ux, uy, T = kt.moments(f[:, r], pb.c1, pb.c2, pb.eta0, pb.gamma)
     fe = kt.feq(rho, ux, uy, T, pb.c1, pb.c2, pb.eta0, pb.gamma)
-    c = F[:, 1:-1, 1:-1]
-    xp, xm = F[:, 1:-1, 2:], F[:, 1:-1, :-2]
-    yp, ym = F[:, 2:, 1:-1], F[:, :-2, 1:-1]
+    c = F[:, r + 1, 1:-1]
+    xp, xm = F[:, r + 1, 2:], F[:, r + 1, :-2]
+    yp, ym = F[:, r + 2, 1:-1], F[:, r, 1:-1]
     dx, dt = pb.dx, pb.dt
     out = []
     for i in range(9):

@@ -1,0 +1,1157 @@
+// HIP kernels and C ABI of the KT D2V9 finite-difference lattice Boltzmann step
+// for gfx950 (MI355X). The ABI is declared and documented in include/lbkt.h.
+//
+// Kernel design: the step is a 5-point cross stencil over 9 SoA planes and is
+// bound by HBM bandwidth (9 loads + 9 stores per site). Each thread owns one
+// column x and marches up a chunk of `rows` rows, keeping the rows y-1, y, y+1
+// of all 9 planes in registers, so every row is read from memory once per
+// chunk; the x-neighbours are re-read from the row just fetched (L1/L2 hits).
+// Boundary ghosts are synthesised in registers. All kernels share one per-site
+// arithmetic routine (kt_site.hpp), so every launch shape and the batched path
+// give bitwise identical results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/lbkt.h"
+#include "kt_site.hpp"
+
+using namespace lbkt;
+
+// ------------------------------------------------------------------ error plumbing
+
+static thread_local std::string g_last_error;
+
+static lb_status fail(lb_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_CHECK(expr)                                                                 \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(LB_EHIP, std::string(#expr ": ") + hipGetErrorString(_e));            \
+  } while (0)
+
+// ------------------------------------------------------------------ host: constants
+
+static int64_t plane_elems(const lb_grid* g) { return g->pitch * (int64_t)g->ny; }
+
+extern "C" int64_t lb_array_elems(const lb_grid* g) {
+  if (!g) return 0;
+  return 9 * plane_elems(g);
+}
+
+extern "C" lb_status lb_default_lambda(lb_grid* g) {
+  if (!g) return fail(LB_EINVAL, "grid is NULL");
+  // Eq. (SEC-VON-13)
+  g->lambda[0] = g->c1 * g->dx;
+  for (int i = 1; i <= 4; ++i) g->lambda[i] = g->c1 * g->dx / 10.0;
+  for (int i = 5; i <= 8; ++i) g->lambda[i] = 0.0;
+  return LB_OK;
+}
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+static lb_status validate_state(const lb_state& s, const char* what) {
+  if (!finite_pos(s.rho) || !finite_pos(s.p) || !std::isfinite(s.ux) || !std::isfinite(s.uy))
+    return fail(LB_EPARAM, std::string(what) + ": state needs rho > 0, p > 0, finite u");
+  return LB_OK;
+}
+
+extern "C" lb_status lb_validate(const lb_grid* g) {
+  if (!g) return fail(LB_EINVAL, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1) return fail(LB_EINVAL, "nx and ny must be >= 1");
+  if (g->pitch < g->nx || g->pitch % 64 != 0)
+    return fail(LB_EINVAL, "pitch must be >= nx and a multiple of 64");
+  if ((double)g->pitch * g->ny * 9.0 * 8.0 >= 4294967296.0)
+    return fail(LB_EUNSUPPORTED, "a distribution array must stay below 4 GiB (9 * pitch * ny * 8 bytes)");
+  if (!finite_pos(g->dx) || !finite_pos(g->dt)) return fail(LB_EPARAM, "dx and dt must be > 0");
+  if (!finite_pos(g->c1) || !finite_pos(g->c2) || !finite_pos(g->eta0))
+    return fail(LB_EPARAM, "c1, c2, eta0 must be > 0");
+  if (g->c1 == g->c2) return fail(LB_EPARAM, "c1 == c2 makes Eqs. (e17)-(e18) singular");
+  if (!finite_pos(g->tau)) return fail(LB_EPARAM, "tau must be > 0");
+  if (!(g->beta >= 0.0 && g->beta <= 0.5)) return fail(LB_EPARAM, "beta must lie in [0, 0.5]");
+  if (!(std::isfinite(g->gamma) && g->gamma > 1.0)) return fail(LB_EPARAM, "gamma must be > 1");
+  for (int i = 0; i < 9; ++i)
+    if (!(std::isfinite(g->lambda[i]) && g->lambda[i] >= 0.0))
+      return fail(LB_EPARAM, "lambda_i must be finite and >= 0");
+  for (int i = 2; i <= 4; ++i)
+    if (g->lambda[i] != g->lambda[1])
+      return fail(LB_EUNSUPPORTED, "lambda_1..lambda_4 must be equal (one value per velocity group)");
+  for (int i = 6; i <= 8; ++i)
+    if (g->lambda[i] != g->lambda[5])
+      return fail(LB_EUNSUPPORTED, "lambda_5..lambda_8 must be equal (one value per velocity group)");
+  for (int e = 0; e < 4; ++e) {
+    const lb_edge& E = g->edge[e];
+    if (E.kind < LB_BC_PERIODIC || E.kind > LB_BC_SHOCK) return fail(LB_EPARAM, "unknown edge kind");
+    if (E.kind == LB_BC_SHOCK && e < 2) return fail(LB_EPARAM, "a SHOCK edge must be a y edge");
+    if (E.split < 0) return fail(LB_EPARAM, "split must be >= 0");
+    if (E.kind == LB_BC_INFLOW || E.kind == LB_BC_SHOCK || E.split > 0) {
+      lb_status s = validate_state(E.a, "edge state a");
+      if (s) return s;
+    }
+    if (E.kind == LB_BC_SHOCK) {
+      lb_status s = validate_state(E.b, "edge state b");
+      if (s) return s;
+      const double a = E.angle_deg * (M_PI / 180.0);
+      if (!(std::isfinite(a) && std::sin(a) != 0.0 && std::tan(a) != 0.0) || !std::isfinite(E.x0) ||
+          !std::isfinite(E.speed))
+        return fail(LB_EPARAM, "bad shock geometry");
+    }
+  }
+  const bool px = g->edge[0].kind == LB_BC_PERIODIC, px2 = g->edge[1].kind == LB_BC_PERIODIC;
+  const bool py = g->edge[2].kind == LB_BC_PERIODIC, py2 = g->edge[3].kind == LB_BC_PERIODIC;
+  if (px != px2 || py != py2) return fail(LB_EPARAM, "both edges of a periodic axis must be periodic");
+  if ((px && g->edge[0].split) || (py && g->edge[2].split) || (px2 && g->edge[1].split) ||
+      (py2 && g->edge[3].split))
+    return fail(LB_EPARAM, "split is not allowed on a periodic edge");
+  return LB_OK;
+}
+
+static void build_consts(const lb_grid* g, KTConsts* K) {
+  std::memset(K, 0, sizeof(*K));
+  K->nx = g->nx;
+  K->ny = g->ny;
+  K->pitch = g->pitch;
+  K->plane = plane_elems(g);
+  const double c1 = g->c1, c2 = g->c2, eta0 = g->eta0;
+  const double b = 2.0 / (g->gamma - 1.0);
+  K->c1 = c1;
+  K->s = c2 * std::sqrt(0.5);
+  K->eta0sq = eta0 * eta0;
+  K->c1sq = c1 * c1;
+  K->c2sq = c2 * c2;
+  K->bval = b;
+  K->inv_b = 1.0 / b;
+  K->inv_tau = 1.0 / g->tau;
+  const double c1s = c1 * c1, c2s = c2 * c2, e2 = eta0 * eta0;
+  // Eq. (e17), A_0 read as (b-2) T / eta0^2
+  K->a0T = (b - 2.0) / e2;
+  K->a1c = -c2s / (4.0 * (c1s - c2s));
+  K->a1T = ((b - 2.0) * c2s / e2 + 2.0) / (4.0 * (c1s - c2s));
+  K->a1u = (c2s / c1s) / (4.0 * (c1s - c2s));
+  K->a5c = -c1s / (4.0 * (c2s - c1s));
+  K->a5T = ((b - 2.0) * c1s / e2 + 2.0) / (4.0 * (c2s - c1s));
+  K->a5u = (c1s / c2s) / (4.0 * (c2s - c1s));
+  // Eq. (e18)
+  K->b1c = -c2s / (2.0 * c1s * (c1s - c2s));
+  K->b1T = (b + 2.0) / (2.0 * c1s * (c1s - c2s));
+  K->b1u = 1.0 / (2.0 * c1s * (c1s - c2s));
+  K->b5c = -c1s / (2.0 * c2s * (c2s - c1s));
+  K->b5T = (b + 2.0) / (2.0 * c2s * (c2s - c1s));
+  K->b5u = 1.0 / (2.0 * c2s * (c2s - c1s));
+  K->d1 = 1.0 / (2.0 * c1s * c1s);
+  K->d5 = 1.0 / (2.0 * c2s * c2s);
+  // Linear stencil: Eqs. (SEC-VON-2a/2b) for the convection, central second
+  // difference for the dissipation, relaxation (f^eq - f)/tau; per velocity group.
+  const double r = g->dt / g->dx, beta = g->beta;
+  const double dx2 = g->dx * g->dx;
+  const double l0 = g->dt * g->lambda[0] / dx2, la = g->dt * g->lambda[1] / dx2, ld = g->dt * g->lambda[5] / dx2;
+  const double base = 1.0 - K->inv_tau;
+  const double sd = K->s;
+  K->l0 = l0;
+  K->wc0 = base - 4.0 * l0;
+  K->la = la;
+  K->wca = (base - 4.0 * la) - r * c1 * (1.0 - 2.0 * beta);
+  K->upa = la + r * c1 * (1.0 - beta);
+  K->dna = la - r * c1 * beta;
+  K->ld = ld;
+  K->wcd = ((base - 4.0 * ld) - r * sd * (1.0 - 2.0 * beta)) - r * sd * (1.0 - 2.0 * beta);
+  K->upd = ld + r * sd * (1.0 - beta);
+  K->dnd = ld - r * sd * beta;
+  for (int e = 0; e < 4; ++e) {
+    const lb_edge& E = g->edge[e];
+    K->kind[e] = E.kind;
+    K->split[e] = E.split;
+    const lb_state* st[2] = {&E.a, &E.b};
+    double* dst[2] = {K->ga[e], K->gb[e]};
+    for (int k = 0; k < 2; ++k) {
+      const double rho = st[k]->rho, ux = st[k]->ux, uy = st[k]->uy;
+      const double T = st[k]->p / rho;
+      const double usq = fma(ux, ux, uy * uy);
+      if (rho > 0.0) feq9(*K, rho, ux, uy, T, usq, dst[k]);
+    }
+  }
+}
+
+// Number of ghost cells behind a moving shock on edge e at time index `step`:
+// ghost cell i is "behind" when (i + 0.5) dx < x0 + y/tan(angle) + speed t/sin(angle).
+static int shock_cells(const lb_grid* g, int e, int64_t step) {
+  const lb_edge& E = g->edge[e];
+  if (E.kind != LB_BC_SHOCK) return 0;
+  const double yg = (e == 2 ? -0.5 : g->ny + 0.5) * g->dx;
+  const double ang = E.angle_deg * (M_PI / 180.0);
+  const double t = (double)step * g->dt;
+  const double xs = E.x0 + yg / std::tan(ang) + E.speed * t / std::sin(ang);
+  const double q = xs / g->dx - 0.5;
+  int n = (q <= 0.0) ? 0 : (q >= (double)g->nx ? g->nx : (int)std::ceil(q));
+  // settle the boundary cell with the exact predicate
+  while (n > 0 && !(((double)(n - 1) + 0.5) * g->dx < xs)) --n;
+  while (n < g->nx && ((double)n + 0.5) * g->dx < xs) ++n;
+  return n;
+}
+
+// ------------------------------------------------------------------ device: loads
+
+// Distribution arrays are addressed through buffer resources: one 32-bit byte
+// offset per lane (row and column) plus a per-plane scalar offset, so the 9
+// planes share a single address register and out-of-range accesses cannot fault
+// (they read 0 / are dropped by the hardware). Arrays must be below 4 GiB.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+#define LB_RSRC_WORD3 0x00020000
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, LB_RSRC_WORD3);
+}
+
+template <typename S> struct Mem;
+template <> struct Mem<double> {
+  static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vb, (int)sb, 0));
+  }
+  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vb, (int)sb, 0);
+  }
+};
+template <> struct Mem<float> {
+  static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
+    return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vb, (int)sb, 0));
+  }
+  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb, double v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)v), r, (int)vb, (int)sb, 0);
+  }
+};
+
+// A distribution array viewed through a buffer resource.
+template <typename S>
+struct View {
+  __amdgpu_buffer_rsrc_t r;
+  uint32_t rowB;    // bytes per row
+  uint32_t planeB;  // bytes per plane
+  __device__ __forceinline__ void load9(uint32_t vb, double v[9]) const {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v[i] = Mem<S>::ld(r, vb, (uint32_t)i * planeB);
+  }
+  __device__ __forceinline__ void store9(uint32_t vb, const double v[9]) const {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Mem<S>::st(r, vb, (uint32_t)i * planeB, v[i]);
+  }
+};
+
+template <typename S>
+__device__ __forceinline__ View<S> make_view(const KTConsts& K, const void* p) {
+  View<S> v;
+  v.rowB = (uint32_t)(K.pitch * sizeof(S));
+  v.planeB = (uint32_t)(K.plane * sizeof(S));
+  v.r = make_rsrc(p, v.planeB * 9u);
+  return v;
+}
+
+// Ghost row of y edge E (2: below row 0, 3: above row ny-1) at column x
+// (vbx = x * sizeof(S)). Edge indices are compile-time constants so no per-lane
+// indexing of K occurs.
+template <int E, typename S>
+__device__ __forceinline__ void ghost_row(const KTConsts& K, const View<S>& f, int x, uint32_t vbx, int ish,
+                                          double r[9]) {
+  const int kind = K.kind[E];
+  if (kind == BC_PERIODIC || kind == BC_OUTFLOW || kind == BC_WALL) {
+    int src;
+    if (kind == BC_PERIODIC)
+      src = (E == 2) ? K.ny - 1 : 0;
+    else
+      src = (E == 2) ? 0 : K.ny - 1;
+    double t[9];
+    f.load9((uint32_t)src * f.rowB + vbx, t);
+    if (kind == BC_WALL) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) r[i] = t[mirror_y(i)];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) r[i] = t[i];
+    }
+  } else {
+    const bool a = (kind == BC_INFLOW) || (x < ish);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = a ? K.ga[E][i] : K.gb[E][i];
+  }
+  if (x < K.split[E]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = K.ga[E][i];
+  }
+}
+
+// Ghost of x edge E (0: left of column 0, 1: right of column nx-1) in row y;
+// cur holds the adjacent interior site. Returns false where the plain load of
+// the clamped / wrapped column already is the ghost (periodic, outflow).
+template <int E>
+__device__ __forceinline__ void ghost_x(const KTConsts& K, int y, const double cur[9], double g[9]) {
+  const int kind = K.kind[E];
+  if (kind == BC_WALL) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = cur[mirror_x(i)];
+  } else if (kind == BC_INFLOW) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = K.ga[E][i];
+  }
+  if (y < K.split[E]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = K.ga[E][i];
+  }
+}
+
+// One row of the march: site (x, y) from prev (y-1), cur (y), nxt (y+1).
+// XEDGE: the block holds column 0 or nx-1 and must synthesise x ghosts.
+template <bool XEDGE, typename S>
+__device__ __forceinline__ void march_row(const KTConsts& K, const View<S>& fi, const View<S>& fo, int x, int y,
+                                          uint32_t vbx, uint32_t vbm, uint32_t vbp, const double prev[9],
+                                          const double cur[9], const double nxt[9]) {
+  const uint32_t rb = (uint32_t)y * fi.rowB;
+  double xm[9], xp[9], out[9];
+  fi.load9(rb + vbm, xm);
+  fi.load9(rb + vbp, xp);
+  if (XEDGE) {
+    if (x == 0) ghost_x<0>(K, y, cur, xm);
+    if (x == K.nx - 1) ghost_x<1>(K, y, cur, xp);
+  }
+  site_update(K, cur, xp, xm, nxt, prev, out);
+  fo.store9(rb + vbx, out);
+}
+
+// March column x from row y0 to y1-1, keeping rows y-1, y, y+1 in registers.
+template <bool XEDGE, typename S>
+__device__ __forceinline__ void march(const KTConsts& K, const View<S>& fi, const View<S>& fo, int x, int y0,
+                                      int y1, int ish_lo, int ish_hi) {
+  const int nx = K.nx, ny = K.ny;
+  const int im = (x > 0) ? x - 1 : (K.kind[0] == BC_PERIODIC ? nx - 1 : 0);
+  const int ip = (x < nx - 1) ? x + 1 : (K.kind[1] == BC_PERIODIC ? 0 : nx - 1);
+  const uint32_t vbx = (uint32_t)x * sizeof(S), vbm = (uint32_t)im * sizeof(S), vbp = (uint32_t)ip * sizeof(S);
+  double prev[9], cur[9], nxt[9];
+  if (y0 > 0)
+    fi.load9((uint32_t)(y0 - 1) * fi.rowB + vbx, prev);
+  else
+    ghost_row<2>(K, fi, x, vbx, ish_lo, prev);
+  fi.load9((uint32_t)y0 * fi.rowB + vbx, cur);
+  const int yfast = min(y1, ny - 1);
+  int y = y0;
+  for (; y < yfast; ++y) {
+    fi.load9((uint32_t)(y + 1) * fi.rowB + vbx, nxt);
+    march_row<XEDGE>(K, fi, fo, x, y, vbx, vbm, vbp, prev, cur, nxt);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      prev[i] = cur[i];
+      cur[i] = nxt[i];
+    }
+  }
+  if (y < y1) {  // y == ny - 1: the row above is the top ghost
+    ghost_row<3>(K, fi, x, vbx, ish_hi, nxt);
+    march_row<XEDGE>(K, fi, fo, x, y, vbx, vbm, vbp, prev, cur, nxt);
+  }
+}
+
+// Block index -> (strip, chunk). With xcd_map, the blocks that the hardware
+// deals round-robin to one XCD (ids congruent mod 8) get one contiguous band of
+// the (chunk, strip) raster, so x- and y-adjacent tiles share that XCD's L2.
+__device__ __forceinline__ void tile_of_block(int id, int nstrips, int nblocks, int xcd_map, int* strip,
+                                              int* chunk) {
+  int lin = id;
+  if (xcd_map) {
+    const int per = nblocks >> 3;
+    lin = (id & 7) * per + (id >> 3);
+  }
+  *strip = lin % nstrips;
+  *chunk = lin / nstrips;
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_step(KTConsts K, const S* __restrict__ fin, S* __restrict__ fout,
+                                              int rows, int nstrips, int nblocks, int xcd_map, int ish_lo,
+                                              int ish_hi) {
+  int strip, chunk;
+  tile_of_block(blockIdx.x, nstrips, nblocks, xcd_map, &strip, &chunk);
+  const int x = strip * blockDim.x + threadIdx.x;
+  if (x >= K.nx) return;
+  const int y0 = chunk * rows;
+  const int y1 = min(y0 + rows, K.ny);
+  const View<S> fi = make_view<S>(K, fin), fo = make_view<S>(K, fout);
+  if (strip == 0 || strip == nstrips - 1)
+    march<true>(K, fi, fo, x, y0, y1, ish_lo, ish_hi);
+  else
+    march<false>(K, fi, fo, x, y0, y1, ish_lo, ish_hi);
+}
+
+template <typename S>
+__device__ __forceinline__ double ldv(const S* p) {
+  return (double)(*p);
+}
+
+template <typename S>
+__device__ __forceinline__ void store9(const KTConsts& K, S* __restrict__ f, int x, int y, const double v[9]) {
+  S* p = f + (int64_t)y * K.pitch + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) p[i * K.plane] = (S)v[i];
+}
+
+// ------------------------------------------------------------------ init / moments / invariants
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_init(KTConsts K, const double* __restrict__ rho,
+                                              const double* __restrict__ ux, const double* __restrict__ uy,
+                                              const double* __restrict__ p, S* __restrict__ f) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= K.nx) return;
+  for (int y = blockIdx.y; y < K.ny; y += gridDim.y) {
+    const int64_t q = (int64_t)y * K.nx + x;
+    const double r = rho[q], u = ux[q], v = uy[q];
+    const double T = p[q] / r;
+    double fe[9];
+    feq9(K, r, u, v, T, fma(u, u, v * v), fe);
+    store9(K, f, x, y, fe);
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_moments(KTConsts K, const S* __restrict__ f, double* rho,
+                                                 double* ux, double* uy, double* T, uint32_t* flags) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int y = blockIdx.y; y < K.ny; y += gridDim.y) {
+  bool bad = false, rneg = false, tneg = false;
+  if (x < K.nx) {
+    const S* p = f + (int64_t)y * K.pitch + x;
+    double c[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) c[i] = ldv(p + i * K.plane);
+    const Prim P = moments9(K, c);
+    const int64_t q = (int64_t)y * K.nx + x;
+    if (rho) rho[q] = P.rho;
+    if (ux) ux[q] = P.ux;
+    if (uy) uy[q] = P.uy;
+    if (T) T[q] = P.T;
+    bad = !(isfinite(P.rho) && isfinite(P.ux) && isfinite(P.uy) && isfinite(P.T));
+    rneg = !(P.rho > 0.0) && !bad;
+    tneg = !(P.T > 0.0) && !bad;
+  }
+  if (flags) {
+    const unsigned long long mb = __ballot(bad), mr = __ballot(rneg), mt = __ballot(tneg);
+    if (__lane_id() == 0 && (mb | mr | mt)) {
+      const uint32_t bits = (mb ? LB_FLAG_NONFINITE : 0u) | (mr ? LB_FLAG_RHO_NONPOS : 0u) |
+                            (mt ? LB_FLAG_T_NONPOS : 0u);
+      atomicOr(flags, bits);
+      if (mb) atomicAdd(flags + 1, (uint32_t)__popcll(mb));
+      if (mr) atomicAdd(flags + 2, (uint32_t)__popcll(mr));
+      if (mt) atomicAdd(flags + 3, (uint32_t)__popcll(mt));
+    }
+  }
+  }
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  const int i = threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Per-block partial sums of (rho, jx, jy, E) over rows [b*rpb, (b+1)*rpb): fixed order.
+template <typename S>
+__global__ __launch_bounds__(256) void k_inv_partial(KTConsts K, const S* __restrict__ f, int rpb,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[4][256];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int y0 = blockIdx.x * rpb, y1 = min(y0 + rpb, K.ny);
+  for (int y = y0; y < y1; ++y) {
+    for (int x = threadIdx.x; x < K.nx; x += blockDim.x) {
+      const S* p = f + (int64_t)y * K.pitch + x;
+      double c[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) c[i] = ldv(p + i * K.plane);
+      const double s14 = (c[1] + c[2]) + (c[3] + c[4]);
+      const double s58 = (c[5] + c[6]) + (c[7] + c[8]);
+      acc[0] += (c[0] + s14) + s58;
+      acc[1] += fma(K.c1, c[3] - c[1], K.s * ((c[6] + c[7]) - (c[5] + c[8])));
+      acc[2] += fma(K.c1, c[4] - c[2], K.s * ((c[7] + c[8]) - (c[5] + c[6])));
+      acc[3] += fma(K.eta0sq, c[0], fma(K.c1sq, s14, K.c2sq * s58));
+    }
+  }
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[(int64_t)blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_inv_final(const double* __restrict__ part, int nblk, double* out4) {
+  __shared__ double sh[4][256];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+    for (int k = 0; k < 4; ++k) acc[k] += part[(int64_t)b * 4 + k];
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out4[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// ------------------------------------------------------------------ adjoint
+
+// Transposed stencil. Site (x, y) receives W(i, k) g_i from every site whose
+// neighbour k it is: from (x-1, y) as its x+dx neighbour (k = 1), from (x+1, y)
+// as k = 2, from (x, y-1) as k = 3 and from (x, y+1) as k = 4, with periodic
+// wrap. Where the site itself supplies a ghost of its own stencil (outflow: a
+// copy; wall: a mirrored copy) it also receives that ghost's share; Dirichlet
+// and shock ghosts do not depend on f and contribute nothing.
+template <int E>
+__device__ __forceinline__ void adj_edge(const KTConsts& K, const double gc[9], int along, double acc[9]) {
+  // k of the ghost that edge E feeds: x- -> 2, x+ -> 1, y- -> 4, y+ -> 3
+  constexpr int k = (E == 0) ? 2 : (E == 1) ? 1 : (E == 2) ? 4 : 3;
+  const int kind = K.kind[E];
+  if (along < K.split[E]) return;
+  if (kind == BC_OUTFLOW) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) acc[i] = fma(wcoef(K, i, k), gc[i], acc[i]);
+  } else if (kind == BC_WALL) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int m = (E < 2) ? mirror_x(i) : mirror_y(i);
+      acc[i] = fma(wcoef(K, m, k), gc[m], acc[i]);
+    }
+  }
+}
+
+// g_n = (dS/df)^T g_np1: transposed stencil over g_np1 plus the local collision adjoint.
+template <typename S>
+__global__ __launch_bounds__(256) void k_adjoint(KTConsts K, const S* __restrict__ fn,
+                                                 const double* __restrict__ g1, double* __restrict__ g0,
+                                                 int rows, int nstrips, int nblocks, int xcd_map) {
+  int strip, chunk;
+  tile_of_block(blockIdx.x, nstrips, nblocks, xcd_map, &strip, &chunk);
+  const int x = strip * blockDim.x + threadIdx.x;
+  if (x >= K.nx) return;
+  const int y0 = chunk * rows;
+  const int y1 = min(y0 + rows, K.ny);
+  const int nx = K.nx, ny = K.ny;
+  const bool perx = (K.kind[0] == BC_PERIODIC), pery = (K.kind[2] == BC_PERIODIC);
+  const bool hasl = (x > 0) || perx, hasr = (x < nx - 1) || perx;
+  const int xl = (x > 0) ? x - 1 : nx - 1, xr = (x < nx - 1) ? x + 1 : 0;
+  for (int y = y0; y < y1; ++y) {
+    const bool hasd = (y > 0) || pery, hasu = (y < ny - 1) || pery;
+    const int yd = (y > 0) ? y - 1 : ny - 1, yu = (y < ny - 1) ? y + 1 : 0;
+    const double* row = g1 + (int64_t)y * K.pitch;
+    const double* rowd = g1 + (int64_t)yd * K.pitch;
+    const double* rowu = g1 + (int64_t)yu * K.pitch;
+    const S* pf = fn + (int64_t)y * K.pitch + x;
+    double gc[9], fc[9], acc[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      gc[i] = row[i * K.plane + x];
+      fc[i] = ldv(pf + i * K.plane);
+    }
+    const Prim P = moments9(K, fc);
+    collision_adjoint(K, P, gc, acc);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const double gu = hasu ? rowu[i * K.plane + x] : 0.0;
+      const double gd = hasd ? rowd[i * K.plane + x] : 0.0;
+      const double gr = hasr ? row[i * K.plane + xr] : 0.0;
+      const double gl = hasl ? row[i * K.plane + xl] : 0.0;
+      double a = acc[i];
+      a = fma(wcoef(K, i, 4), gu, a);
+      a = fma(wcoef(K, i, 3), gd, a);
+      a = fma(wcoef(K, i, 2), gr, a);
+      a = fma(wcoef(K, i, 1), gl, a);
+      acc[i] = fma(wcoef(K, i, 0), gc[i], a);
+    }
+    if (x == 0 && !perx) adj_edge<0>(K, gc, y, acc);
+    if (x == nx - 1 && !perx) adj_edge<1>(K, gc, y, acc);
+    if (y == 0 && !pery) adj_edge<2>(K, gc, x, acc);
+    if (y == ny - 1 && !pery) adj_edge<3>(K, gc, x, acc);
+    double* po = g0 + (int64_t)y * K.pitch + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) po[i * K.plane] = acc[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_init_adjoint(KTConsts K, const double* __restrict__ rho,
+                                                      const double* __restrict__ ux,
+                                                      const double* __restrict__ uy,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ g,
+                                                      double* __restrict__ grho) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= K.nx) return;
+  for (int y = blockIdx.y; y < K.ny; y += gridDim.y) {
+    const int64_t q = (int64_t)y * K.nx + x;
+    const double* pg = g + (int64_t)y * K.pitch + x;
+    double gv[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) gv[i] = pg[i * K.plane];
+    grho[q] = init_adjoint_site(K, rho[q], ux[q], uy[q], p[q], gv);
+  }
+}
+
+// ------------------------------------------------------------------ batched
+
+struct WorkItem {
+  int32_t prob;
+  int32_t strip;
+};
+
+struct ProbInfo {
+  int64_t offset;   // element offset of the problem's array in the packed buffer
+};
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_step_batched(const KTConsts* __restrict__ Ks,
+                                                      const ProbInfo* __restrict__ info,
+                                                      const WorkItem* __restrict__ items, const S* fin, S* fout) {
+  const WorkItem w = items[blockIdx.x];
+  const KTConsts& K = Ks[w.prob];
+  const int64_t off = info[w.prob].offset;
+  const int x = w.strip * blockDim.x + threadIdx.x;
+  if (x >= K.nx) return;
+  const View<S> fi = make_view<S>(K, fin + off), fo = make_view<S>(K, fout + off);
+  const int nstrips = (K.nx + blockDim.x - 1) / blockDim.x;
+  if (w.strip == 0 || w.strip == nstrips - 1)
+    march<true>(K, fi, fo, x, 0, K.ny, 0, 0);
+  else
+    march<false>(K, fi, fo, x, 0, K.ny, 0, 0);
+}
+
+// ------------------------------------------------------------------ host launch helpers
+
+static size_t elem_size(lb_prec p) { return p == LB_F32 ? 4 : 8; }
+
+static lb_status check_ptr(const void* p, const char* what) {
+  if (!p) return fail(LB_EINVAL, std::string(what) + " is NULL");
+  if (((uintptr_t)p) % 256 != 0) return fail(LB_EINVAL, std::string(what) + " must be 256-byte aligned");
+  return LB_OK;
+}
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+static lb_status resolve_tile(const lb_tile* tile, int ny, int* bx, int* rows) {
+  int b = 256, r = 32;
+  if (tile && (tile->block_x || tile->rows)) {
+    b = tile->block_x;
+    r = tile->rows;
+  }
+  if (b != 64 && b != 128 && b != 256) return fail(LB_EINVAL, "tile block_x must be 64, 128 or 256");
+  if (r < 1) return fail(LB_EINVAL, "tile rows must be >= 1");
+  *bx = b;
+  *rows = std::min(r, ny);
+  return LB_OK;
+}
+
+static lb_status launch_step(const lb_grid* g, const KTConsts& K, lb_prec prec, const void* fin, void* fout,
+                             int64_t step, int bx, int rows, hipStream_t st) {
+  const int nstrips = (g->nx + bx - 1) / bx;
+  const int nchunks = (g->ny + rows - 1) / rows;
+  const int64_t nblocks64 = (int64_t)nstrips * nchunks;
+  if (nblocks64 > 0x7fffffff) return fail(LB_EINVAL, "grid too large for one launch");
+  const int nblocks = (int)nblocks64;
+  const int xcd_map = (nblocks % 8 == 0 && nchunks % 8 == 0) ? 1 : 0;
+  const int ish_lo = shock_cells(g, 2, step), ish_hi = shock_cells(g, 3, step);
+  if (prec == LB_F64)
+    hipLaunchKernelGGL(k_step<double>, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fin, (double*)fout,
+                       rows, nstrips, nblocks, xcd_map, ish_lo, ish_hi);
+  else
+    hipLaunchKernelGGL(k_step<float>, dim3(nblocks), dim3(bx), 0, st, K, (const float*)fin, (float*)fout,
+                       rows, nstrips, nblocks, xcd_map, ish_lo, ish_hi);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
+static lb_status check_prec(lb_prec p) {
+  if (p != LB_F64 && p != LB_F32) return fail(LB_EINVAL, "unknown precision");
+  return LB_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" lb_status lb_init(const lb_grid* g, lb_prec prec, const double* rho, const double* ux,
+                             const double* uy, const double* p, void* f, void* stream) {
+  lb_status s;
+  if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(f, "f"))) return s;
+  if (!rho || !ux || !uy || !p) return fail(LB_EINVAL, "field pointer is NULL");
+  KTConsts K;
+  build_consts(g, &K);
+  const dim3 grid((g->nx + 255) / 256, std::min(g->ny, 65535));
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LB_F64)
+    hipLaunchKernelGGL(k_init<double>, grid, dim3(256), 0, st, K, rho, ux, uy, p, (double*)f);
+  else
+    hipLaunchKernelGGL(k_init<float>, grid, dim3(256), 0, st, K, rho, ux, uy, p, (float*)f);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
+extern "C" lb_status lb_step_tiled(const lb_grid* g, lb_prec prec, const void* fin, void* fout, int64_t step,
+                                   const lb_tile* tile, void* stream) {
+  lb_status s;
+  if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(fin, "f_in")) ||
+      (s = check_ptr(fout, "f_out")))
+    return s;
+  const size_t bytes = (size_t)lb_array_elems(g) * elem_size(prec);
+  if (overlap(fin, bytes, fout, bytes)) return fail(LB_EALIAS, "f_in and f_out overlap");
+  int bx, rows;
+  if ((s = resolve_tile(tile, g->ny, &bx, &rows))) return s;
+  KTConsts K;
+  build_consts(g, &K);
+  return launch_step(g, K, prec, fin, fout, step, bx, rows, (hipStream_t)stream);
+}
+
+extern "C" lb_status lb_step(const lb_grid* g, lb_prec prec, const void* fin, void* fout, int64_t step,
+                             void* stream) {
+  return lb_step_tiled(g, prec, fin, fout, step, nullptr, stream);
+}
+
+namespace {
+struct GraphEntry {
+  std::string key;
+  hipGraphExec_t exec = nullptr;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;  // small LRU of captured step loops
+}  // namespace
+
+static std::string run_key(const lb_grid* g, lb_prec prec, const void* fa, const void* fb, int64_t step0,
+                           int nsteps, int bx, int rows, void* stream) {
+  std::string k((const char*)g, sizeof(lb_grid));
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "|%d|%p|%p|%lld|%d|%d|%d|%p", (int)prec, fa, fb, (long long)step0, nsteps, bx,
+                rows, stream);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return k + buf + std::to_string(dev);
+}
+
+extern "C" lb_status lb_run(const lb_grid* g, lb_prec prec, void* fa, void* fb, int64_t step0, int32_t nsteps,
+                            int32_t use_graph, const lb_tile* tile, void* stream) {
+  lb_status s;
+  if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(fa, "f_a")) || (s = check_ptr(fb, "f_b")))
+    return s;
+  if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
+  const size_t bytes = (size_t)lb_array_elems(g) * elem_size(prec);
+  if (overlap(fa, bytes, fb, bytes)) return fail(LB_EALIAS, "f_a and f_b overlap");
+  int bx, rows;
+  if ((s = resolve_tile(tile, g->ny, &bx, &rows))) return s;
+  KTConsts K;
+  build_consts(g, &K);
+  hipStream_t st = (hipStream_t)stream;
+  if (!use_graph || st == nullptr || nsteps == 0) {
+    for (int n = 0; n < nsteps; ++n) {
+      const void* in = (n % 2 == 0) ? fa : fb;
+      void* out = (n % 2 == 0) ? fb : fa;
+      if ((s = launch_step(g, K, prec, in, out, step0 + n, bx, rows, st))) return s;
+    }
+    return LB_OK;
+  }
+  const std::string key = run_key(g, prec, fa, fb, step0, nsteps, bx, rows, stream);
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  for (auto& e : g_graphs)
+    if (e.key == key) {
+      HIP_CHECK(hipGraphLaunch(e.exec, st));
+      return LB_OK;
+    }
+  HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  lb_status ls = LB_OK;
+  for (int n = 0; n < nsteps && ls == LB_OK; ++n) {
+    const void* in = (n % 2 == 0) ? fa : fb;
+    void* out = (n % 2 == 0) ? fb : fa;
+    ls = launch_step(g, K, prec, in, out, step0 + n, bx, rows, st);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t ce = hipStreamEndCapture(st, &graph);
+  if (ls != LB_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return ls;
+  }
+  if (ce != hipSuccess) return fail(LB_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+  hipGraphExec_t exec = nullptr;
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return fail(LB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+  if (g_graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(g_graphs.front().exec);
+    g_graphs.erase(g_graphs.begin());
+  }
+  g_graphs.push_back({key, exec});
+  HIP_CHECK(hipGraphLaunch(exec, st));
+  return LB_OK;
+}
+
+extern "C" lb_status lb_moments(const lb_grid* g, lb_prec prec, const void* f, double* rho, double* ux,
+                                double* uy, double* T, uint32_t* flags, void* stream) {
+  lb_status s;
+  if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(f, "f"))) return s;
+  KTConsts K;
+  build_consts(g, &K);
+  hipStream_t st = (hipStream_t)stream;
+  if (flags) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, flags, 4);
+    HIP_CHECK(hipGetLastError());
+  }
+  const dim3 grid((g->nx + 255) / 256, std::min(g->ny, 65535));
+  if (prec == LB_F64)
+    hipLaunchKernelGGL(k_moments<double>, grid, dim3(256), 0, st, K, (const double*)f, rho, ux, uy, T, flags);
+  else
+    hipLaunchKernelGGL(k_moments<float>, grid, dim3(256), 0, st, K, (const float*)f, rho, ux, uy, T, flags);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
+namespace {
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<int, Workspace> g_ws;
+}  // namespace
+
+static lb_status workspace(size_t bytes, void** out) {
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  Workspace& w = g_ws[dev];
+  if (w.bytes < bytes) {
+    if (w.ptr) HIP_CHECK(hipFree(w.ptr));
+    w.ptr = nullptr;
+    w.bytes = 0;
+    if (hipMalloc(&w.ptr, bytes) != hipSuccess) return fail(LB_ENOMEM, "workspace allocation failed");
+    w.bytes = bytes;
+  }
+  *out = w.ptr;
+  return LB_OK;
+}
+
+extern "C" lb_status lb_invariants(const lb_grid* g, lb_prec prec, const void* f, double* out4, void* stream) {
+  lb_status s;
+  if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(f, "f"))) return s;
+  if (!out4) return fail(LB_EINVAL, "out4 is NULL");
+  KTConsts K;
+  build_consts(g, &K);
+  const int nblk = std::min(g->ny, 4096);
+  const int rpb = (g->ny + nblk - 1) / nblk;
+  const int nb = (g->ny + rpb - 1) / rpb;
+  void* part = nullptr;
+  if ((s = workspace((size_t)nb * 4 * sizeof(double), &part))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LB_F64)
+    hipLaunchKernelGGL(k_inv_partial<double>, dim3(nb), dim3(256), 0, st, K, (const double*)f, rpb, (double*)part);
+  else
+    hipLaunchKernelGGL(k_inv_partial<float>, dim3(nb), dim3(256), 0, st, K, (const float*)f, rpb, (double*)part);
+  HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_inv_final, dim3(1), dim3(256), 0, st, (const double*)part, nb, out4);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
+extern "C" lb_status lb_step_adjoint(const lb_grid* g, lb_prec prec, const void* fn, const double* g1, double* g0,
+                                     int64_t step, void* stream) {
+  (void)step;  // the step's dependence on t (SHOCK ghosts) does not involve f
+  lb_status s;
+  if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(fn, "f_n")) ||
+      (s = check_ptr(g1, "g_np1")) || (s = check_ptr(g0, "g_n")))
+    return s;
+  const size_t gbytes = (size_t)lb_array_elems(g) * 8;
+  if (overlap(g1, gbytes, g0, gbytes)) return fail(LB_EALIAS, "g_np1 and g_n overlap");
+  KTConsts K;
+  build_consts(g, &K);
+  const int bx = 256, rows = std::min(32, g->ny);
+  const int nstrips = (g->nx + bx - 1) / bx;
+  const int nchunks = (g->ny + rows - 1) / rows;
+  const int nblocks = nstrips * nchunks;
+  const int xcd_map = (nblocks % 8 == 0 && nchunks % 8 == 0) ? 1 : 0;
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LB_F64)
+    hipLaunchKernelGGL(k_adjoint<double>, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fn, g1, g0, rows,
+                       nstrips, nblocks, xcd_map);
+  else
+    hipLaunchKernelGGL(k_adjoint<float>, dim3(nblocks), dim3(bx), 0, st, K, (const float*)fn, g1, g0, rows,
+                       nstrips, nblocks, xcd_map);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
+extern "C" lb_status lb_init_adjoint(const lb_grid* g, const double* rho, const double* ux, const double* uy,
+                                     const double* p, const double* gf0, double* grho, void* stream) {
+  lb_status s;
+  if ((s = lb_validate(g)) || (s = check_ptr(gf0, "g_f0"))) return s;
+  if (!rho || !ux || !uy || !p || !grho) return fail(LB_EINVAL, "field pointer is NULL");
+  KTConsts K;
+  build_consts(g, &K);
+  const dim3 grid((g->nx + 255) / 256, std::min(g->ny, 65535));
+  hipLaunchKernelGGL(k_init_adjoint, grid, dim3(256), 0, (hipStream_t)stream, K, rho, ux, uy, p, gf0, grho);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
+// ------------------------------------------------------------------ batch
+
+struct lb_batch {
+  int nprob = 0;
+  lb_prec prec = LB_F32;
+  std::vector<lb_grid> grids;
+  std::vector<int64_t> offsets, pitches;
+  int64_t total = 0;
+  int block_x = 256;
+  int dev = 0;
+  KTConsts* d_consts = nullptr;
+  ProbInfo* d_info = nullptr;
+  WorkItem* d_items = nullptr;
+  int nitems = 0;
+  int64_t step = 0;
+  // captured graph
+  hipGraphExec_t exec = nullptr;
+  void* g_fa = nullptr;
+  void* g_fb = nullptr;
+  int g_nsteps = -1;
+  int g_bx = 0;
+  void* g_stream = nullptr;
+};
+
+static lb_status batch_items(lb_batch* b) {
+  std::vector<WorkItem> items;
+  // longest problems first so the tail of a launch is made of short items
+  std::vector<int> order(b->nprob);
+  for (int p = 0; p < b->nprob; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return b->grids[a].nx * (int64_t)b->grids[a].ny > b->grids[c].nx * (int64_t)b->grids[c].ny; });
+  for (int p : order) {
+    const int ns = (b->grids[p].nx + b->block_x - 1) / b->block_x;
+    for (int s = 0; s < ns; ++s) items.push_back({p, s});
+  }
+  if (b->d_items) HIP_CHECK(hipFree(b->d_items));
+  b->d_items = nullptr;
+  HIP_CHECK(hipMalloc(&b->d_items, items.size() * sizeof(WorkItem)));
+  HIP_CHECK(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+  b->nitems = (int)items.size();
+  return LB_OK;
+}
+
+extern "C" lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, lb_prec prec, lb_batch** out) {
+  if (!out) return fail(LB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nprob < 1 || !grids) return fail(LB_EINVAL, "need nprob >= 1 grids");
+  lb_status s;
+  if ((s = check_prec(prec))) return s;
+  lb_batch* b = new (std::nothrow) lb_batch();
+  if (!b) return fail(LB_ENOMEM, "batch allocation failed");
+  b->nprob = nprob;
+  b->prec = prec;
+  b->grids.assign(grids, grids + nprob);
+  int64_t off = 0;
+  std::vector<KTConsts> ks(nprob);
+  std::vector<ProbInfo> info(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    lb_grid& g = b->grids[p];
+    g.pitch = ((int64_t)g.nx + 63) / 64 * 64;
+    if ((s = lb_validate(&g))) {
+      delete b;
+      return fail(s, "problem " + std::to_string(p) + ": " + g_last_error);
+    }
+    for (int e = 0; e < 4; ++e)
+      if (g.edge[e].kind == LB_BC_SHOCK) {
+        delete b;
+        return fail(LB_EUNSUPPORTED, "batched problems cannot have SHOCK edges");
+      }
+    b->offsets.push_back(off);
+    b->pitches.push_back(g.pitch);
+    info[p].offset = off;
+    build_consts(&g, &ks[p]);
+    off += lb_array_elems(&g);
+  }
+  b->total = off;
+  (void)hipGetDevice(&b->dev);
+  if (hipMalloc(&b->d_consts, sizeof(KTConsts) * nprob) != hipSuccess ||
+      hipMalloc(&b->d_info, sizeof(ProbInfo) * nprob) != hipSuccess) {
+    lb_batch_destroy(b);
+    return fail(LB_ENOMEM, "batch metadata allocation failed");
+  }
+  if (hipMemcpy(b->d_consts, ks.data(), sizeof(KTConsts) * nprob, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_info, info.data(), sizeof(ProbInfo) * nprob, hipMemcpyHostToDevice) != hipSuccess) {
+    lb_batch_destroy(b);
+    return fail(LB_EHIP, "batch metadata upload failed");
+  }
+  if ((s = batch_items(b))) {
+    lb_batch_destroy(b);
+    return s;
+  }
+  *out = b;
+  return LB_OK;
+}
+
+extern "C" lb_status lb_batch_layout(const lb_batch* b, int64_t* offsets, int64_t* pitches, int64_t* total) {
+  if (!b) return fail(LB_EINVAL, "batch is NULL");
+  if (offsets) std::copy(b->offsets.begin(), b->offsets.end(), offsets);
+  if (pitches) std::copy(b->pitches.begin(), b->pitches.end(), pitches);
+  if (total) *total = b->total;
+  return LB_OK;
+}
+
+extern "C" lb_status lb_batch_set_tile(lb_batch* b, const lb_tile* tile) {
+  if (!b) return fail(LB_EINVAL, "batch is NULL");
+  int bx = 256;
+  if (tile && tile->block_x) bx = tile->block_x;
+  if (bx != 64 && bx != 128 && bx != 256) return fail(LB_EINVAL, "tile block_x must be 64, 128 or 256");
+  if (bx == b->block_x) return LB_OK;
+  b->block_x = bx;
+  return batch_items(b);
+}
+
+static lb_status launch_batched(lb_batch* b, const void* fin, void* fout, hipStream_t st) {
+  if (b->prec == LB_F64)
+    hipLaunchKernelGGL(k_step_batched<double>, dim3(b->nitems), dim3(b->block_x), 0, st, b->d_consts, b->d_info,
+                       b->d_items, (const double*)fin, (double*)fout);
+  else
+    hipLaunchKernelGGL(k_step_batched<float>, dim3(b->nitems), dim3(b->block_x), 0, st, b->d_consts, b->d_info,
+                       b->d_items, (const float*)fin, (float*)fout);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
+extern "C" lb_status lb_step_batched(lb_batch* b, void* fa, void* fb, int32_t nsteps, void* stream) {
+  if (!b) return fail(LB_EINVAL, "batch is NULL");
+  lb_status s;
+  if ((s = check_ptr(fa, "f_a")) || (s = check_ptr(fb, "f_b"))) return s;
+  if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
+  const size_t bytes = (size_t)b->total * elem_size(b->prec);
+  if (overlap(fa, bytes, fb, bytes)) return fail(LB_EALIAS, "f_a and f_b overlap");
+  hipStream_t st = (hipStream_t)stream;
+  if (nsteps == 0) return LB_OK;
+  if (st == nullptr) {
+    for (int n = 0; n < nsteps; ++n)
+      if ((s = launch_batched(b, (n % 2 == 0) ? fa : fb, (n % 2 == 0) ? fb : fa, st))) return s;
+    b->step += nsteps;
+    return LB_OK;
+  }
+  if (!(b->exec && b->g_fa == fa && b->g_fb == fb && b->g_nsteps == nsteps && b->g_bx == b->block_x &&
+        b->g_stream == stream)) {
+    if (b->exec) HIP_CHECK(hipGraphExecDestroy(b->exec));
+    b->exec = nullptr;
+    HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    lb_status ls = LB_OK;
+    for (int n = 0; n < nsteps && ls == LB_OK; ++n)
+      ls = launch_batched(b, (n % 2 == 0) ? fa : fb, (n % 2 == 0) ? fb : fa, st);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (ls != LB_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return ls;
+    }
+    if (ce != hipSuccess) return fail(LB_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    hipError_t ie = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(LB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    b->g_fa = fa;
+    b->g_fb = fb;
+    b->g_nsteps = nsteps;
+    b->g_bx = b->block_x;
+    b->g_stream = stream;
+  }
+  HIP_CHECK(hipGraphLaunch(b->exec, st));
+  b->step += nsteps;
+  return LB_OK;
+}
+
+extern "C" void lb_batch_destroy(lb_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->d_consts) (void)hipFree(b->d_consts);
+  if (b->d_info) (void)hipFree(b->d_info);
+  if (b->d_items) (void)hipFree(b->d_items);
+  delete b;
+}
+
+// ------------------------------------------------------------------ autotuner
+
+extern "C" lb_status lb_autotune(const lb_grid* g, lb_prec prec, void* fa, void* fb, int32_t reps, lb_tile* best,
+                                 float* best_ms, void* stream) {
+  lb_status s;
+  if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(fa, "f_a")) || (s = check_ptr(fb, "f_b")))
+    return s;
+  if (!best) return fail(LB_EINVAL, "best is NULL");
+  if (reps < 1) reps = 1;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  const int bxs[3] = {64, 128, 256};
+  const int rws[6] = {4, 8, 16, 32, 64, 128};
+  float bestv = 1e30f;
+  lb_tile bt = {256, 32};
+  KTConsts K;
+  build_consts(g, &K);
+  for (int bi = 0; bi < 3; ++bi)
+    for (int ri = 0; ri < 6; ++ri) {
+      const int bx = bxs[bi], rows = std::min(rws[ri], g->ny);
+      if (ri > 0 && rows == std::min(rws[ri - 1], g->ny)) continue;
+      // warm-up launch, then reps timed launches
+      if ((s = launch_step(g, K, prec, fa, fb, 0, bx, rows, st))) goto done;
+      if (hipEventRecord(e0, st) != hipSuccess) { s = fail(LB_EHIP, "event record"); goto done; }
+      for (int n = 0; n < reps; ++n)
+        if ((s = launch_step(g, K, prec, (n % 2 == 0) ? fb : fa, (n % 2 == 0) ? fa : fb, 0, bx, rows, st))) goto done;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        s = fail(LB_EHIP, "event sync");
+        goto done;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms /= reps;
+      if (ms < bestv) {
+        bestv = ms;
+        bt.block_x = bx;
+        bt.rows = rows;
+      }
+    }
+done:
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s) return s;
+  *best = bt;
+  if (best_ms) *best_ms = bestv;
+  return LB_OK;
+}
+
+extern "C" int64_t lb_struct_size(int32_t which) {
+  switch (which) {
+    case 0: return (int64_t)sizeof(lb_grid);
+    case 1: return (int64_t)sizeof(lb_edge);
+    case 2: return (int64_t)sizeof(lb_state);
+    case 3: return (int64_t)sizeof(lb_tile);
+  }
+  return -1;
+}
+
+extern "C" const char* lb_status_str(lb_status s) {
+  switch (s) {
+    case LB_OK: return "LB_OK";
+    case LB_EINVAL: return "LB_EINVAL";
+    case LB_EPARAM: return "LB_EPARAM";
+    case LB_EALIAS: return "LB_EALIAS";
+    case LB_ENONFINITE: return "LB_ENONFINITE";
+    case LB_EHIP: return "LB_EHIP";
+    case LB_ENOMEM: return "LB_ENOMEM";
+    case LB_EUNSUPPORTED: return "LB_EUNSUPPORTED";
+  }
+  return "LB_?";
+}
+
+extern "C" const char* lb_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,78 @@
+"""Shared helpers of the GPU parity tests (comparison rules and runners)."""
+from __future__ import annotations
+
+import functools
+import sys
+
+import numpy as np
+import torch
+
+from oracle import scheme
+from workloads import problems as P
+
+F64 = torch.float64
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def compare_fields(got, want, tol):
+    """Relative comparison: rho and T pointwise, u against the field's max modulus.
+
+    got / want = (rho, ux, uy, T) tensors on the CPU. Returns the worst errors.
+    """
+    r, ux, uy, T = [g.cpu().to(F64) for g in got]
+    R, UX, UY, TT = [w.cpu().to(F64) for w in want]
+    e_r = float(((r - R).abs() / R.abs()).max())
+    umax = float(torch.maximum(UX.abs().max(), UY.abs().max()))
+    e_u = float(torch.maximum((ux - UX).abs().max(), (uy - UY).abs().max())) / max(umax, 1e-300)
+    e_T = float(((T - TT).abs() / TT.abs()).max())
+    errs = {"rho": e_r, "u": e_u, "T": e_T}
+    assert all(np.isfinite(v) for v in errs.values()), errs
+    assert e_r <= tol and e_u <= tol and e_T <= tol, errs
+    return errs
+
+
+def rel_l1(a, b):
+    a = a.cpu().to(F64)
+    b = b.cpu().to(F64)
+    return float((a - b).abs().sum() / b.abs().sum())
+
+
+@functools.lru_cache(maxsize=16)
+def _oracle_cached(key):
+    cfg, nsteps = _CFG_REGISTRY[key]
+    pb = scheme.Problem.from_dict(cfg)
+    f = scheme.init(pb, *P.init_fields(cfg))
+    f = scheme.run(pb, f, nsteps)
+    return scheme.fields(pb, f), f
+
+
+_CFG_REGISTRY = {}
+
+
+def oracle_run(name, cfg, nsteps):
+    """Oracle fields after nsteps from the workload's initial fields (cached per name)."""
+    _CFG_REGISTRY[name] = (cfg, nsteps)
+    return _oracle_cached(name)
+
+
+def gpu_run(cfg, nsteps, prec="f64", tile=None, use_graph=False, fields=None):
+    import paper_0706_0405_amd as lb
+    dev = torch.device("cuda", 0)
+    g = lb.Grid.from_workload(cfg)
+    fl = P.init_fields(cfg) if fields is None else fields
+    rho, ux, uy, p = [torch.tensor(np.ascontiguousarray(a), dtype=F64, device=dev) for a in fl]
+    fa = lb.init(g, rho, ux, uy, p, prec=prec)
+    fb = lb.empty(g, prec, dev)
+    out = lb.run(g, fa, fb, nsteps, prec=prec, tile=tile, use_graph=use_graph)
+    return g, out
+
+
+def gpu_fields(g, f, prec):
+    import paper_0706_0405_amd as lb
+    r, ux, uy, T, flags = lb.moments(g, f, prec=prec)
+    torch.cuda.synchronize()
+    return (r, ux, uy, T), flags.cpu()

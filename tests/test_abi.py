@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol that
+include/lbkt.h declares, its structures match the binding, and host validation
+rejects bad input before any launch. No GPU is needed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_0706_0405_amd import _lib
+from paper_0706_0405_amd.api import Grid
+from workloads import problems as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "lbkt.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    L = _lib.lib()
+    names = _header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTED)
+
+
+def test_struct_layout_matches_binding():
+    L = _lib.lib()
+    assert L.lb_struct_size(0) == ctypes.sizeof(_lib.LbGrid)
+    assert L.lb_struct_size(1) == ctypes.sizeof(_lib.LbEdge)
+    assert L.lb_struct_size(2) == ctypes.sizeof(_lib.LbState)
+    assert L.lb_struct_size(3) == ctypes.sizeof(_lib.LbTile)
+    assert L.lb_struct_size(9) == -1
+
+
+def _grid(**kw):
+    cfg = P.sod(nx=100, ny=4)
+    cfg.update(kw)
+    return Grid.from_workload(cfg)
+
+
+def _status(g):
+    return _lib.lib().lb_validate(ctypes.byref(g))
+
+
+def test_default_lambda_is_eq13():
+    g = _grid().c()
+    lam = [g.lam[i] for i in range(9)]
+    c1dx = g.c1 * g.dx
+    assert lam == [c1dx] + [c1dx / 10.0] * 4 + [0.0] * 4
+
+
+def test_validate_accepts_workloads():
+    for cfg in (P.sod(), P.ratio1000(), P.regular_reflection(), P.double_mach(), P.roofline_grid(),
+                P.periodic_smooth()):
+        assert _status(Grid.from_workload(cfg).c()) == 0
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("c2", 1.0, -2),           # c1 == c2 is singular in Eqs. (e17)-(e18)
+    ("beta", 0.6, -2),
+    ("beta", -0.1, -2),
+    ("tau", 0.0, -2),
+    ("gamma", 1.0, -2),
+    ("dt", -1.0, -2),
+    ("eta0", 0.0, -2),
+])
+def test_validate_rejects_parameters(field, value, status):
+    cfg = P.sod(nx=100, ny=4)
+    cfg[field] = value
+    assert _status(Grid.from_workload(cfg).c()) == status
+
+
+def test_validate_rejects_layout_and_edges():
+    g = _grid().c()
+    g.pitch = 100                                 # not a multiple of 64
+    assert _status(g) == -1
+    g = _grid().c()
+    g.nx = 0
+    assert _status(g) == -1
+    g = _grid().c()
+    g.edge[0].kind = _lib.BC["periodic"]          # only one periodic x edge
+    assert _status(g) == -2
+    g = _grid().c()
+    g.edge[0].kind = _lib.BC["shock"]             # shock edges are y edges
+    assert _status(g) == -2
+    g = _grid().c()
+    g.lam[2] = 0.5                                # lambda differs inside the axis group
+    assert _status(g) == -7
+    g = _grid().c()
+    g.edge[2].split = 3                           # split on a periodic edge
+    assert _status(g) == -2
+    cfg = P.double_mach(nx=96, ny=24)
+    g = Grid.from_workload(cfg).c()
+    g.edge[3].b.rho = -1.0                        # bad shock state
+    assert _status(g) == -2
+    g = _grid(nx=8192 * 8, ny=2048).c()           # 9 planes over 4 GiB
+    assert _status(g) == -7
+
+
+def test_alias_and_alignment_rejected_before_launch():
+    L = _lib.lib()
+    g = _grid().c()
+    buf = ctypes.c_void_p(1 << 20)   # never dereferenced: the call returns before any launch
+    st = L.lb_step(ctypes.byref(g), 0, buf, buf, 0, None)
+    assert st == -3 and b"overlap" in L.lb_last_error()
+    st = L.lb_step(ctypes.byref(g), 0, ctypes.c_void_p((1 << 20) + 8), ctypes.c_void_p(1 << 30), 0, None)
+    assert st == -1 and b"aligned" in L.lb_last_error()
+    st = L.lb_step(ctypes.byref(g), 7, buf, ctypes.c_void_p(1 << 30), 0, None)
+    assert st == -1
+    assert L.lb_status_str(-4) == b"LB_ENONFINITE"
+
+
+def test_array_elems():
+    g = _grid(nx=100, ny=4).c()
+    assert g.pitch == 128
+    assert _lib.lib().lb_array_elems(ctypes.byref(g)) == 9 * 128 * 4

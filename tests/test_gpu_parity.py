@@ -1,0 +1,269 @@
+"""GPU parity: the HIP step (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 storage within 1e-12 relative on rho and T pointwise and on u
+against its maximum modulus; FP32 storage (FP64 arithmetic) within a relative
+L1 density error of 1e-6 against the FP64 oracle. Bitwise checks: every launch
+shape and the graph path agree exactly, and y-uniform data stay y-uniform.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import kt, scheme
+from workloads import problems as P
+
+from tests._util import F64, compare_fields, gpu_fields, gpu_run, oracle_run, rel_l1, say
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _lb():
+    import paper_0706_0405_amd as lb
+    return lb
+
+
+# ------------------------------------------------------------------ configs at their own size
+
+CASES = {
+    "sod": (P.sod(), 500),
+    "ratio1000": (P.ratio1000(), 4000),
+    "regular_reflection": (P.regular_reflection(), 300),
+    "double_mach": (P.double_mach(), 40),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_matches_oracle(name):
+    cfg, n = CASES[name]
+    say("case", name, cfg["nx"], cfg["ny"], n)
+    g, f = gpu_run(cfg, n, "f64")
+    got, flags = gpu_fields(g, f, "f64")
+    assert int(flags[0]) & 1 == 0
+    want, _ = oracle_run(name, cfg, n)
+    errs = compare_fields(got, want, 1e-12)
+    say(name, "fp64 errors", errs)
+
+
+@pytest.mark.parametrize("name,bound", [("sod", 1e-6), ("ratio1000", 1e-6), ("regular_reflection", 1e-6),
+                                        ("double_mach", 1e-6)])
+def test_fp32_storage_l1_bound(name, bound):
+    cfg, n = CASES[name]
+    say("case", name, "f32", n)
+    g, f = gpu_run(cfg, n, "f32")
+    got, flags = gpu_fields(g, f, "f32")
+    assert int(flags[0]) & 1 == 0
+    want, _ = oracle_run(name, cfg, n)
+    e = rel_l1(got[0], want[0])
+    say(name, "fp32 storage rel L1(rho)", e)
+    assert e <= bound
+
+
+# ------------------------------------------------------------------ boundary matrix, ragged sizes
+
+def _edge(kind, **kw):
+    d = {"kind": kind, "split": 0, "a": (1.2, 0.3, -0.1, 0.9), "b": (0.8, -0.2, 0.1, 1.1),
+         "x0": 0.05, "angle_deg": 60.0, "speed": 1.5}
+    d.update(kw)
+    return d
+
+
+BC_SETS = {
+    "periodic": [_edge("periodic"), _edge("periodic"), _edge("periodic"), _edge("periodic")],
+    "walls": [_edge("wall"), _edge("wall"), _edge("wall"), _edge("wall")],
+    "outflow": [_edge("outflow"), _edge("outflow"), _edge("outflow"), _edge("outflow")],
+    "inflow": [_edge("inflow"), _edge("inflow", a=(0.9, -0.4, 0.2, 1.3)), _edge("inflow", a=(1.1, 0.1, 0.3, 1.0)),
+               _edge("inflow", a=(1.0, 0.2, -0.3, 0.8))],
+    "mixed_split": [_edge("inflow"), _edge("outflow"), _edge("wall", split=5), _edge("shock")],
+    "walls_split": [_edge("wall", split=3), _edge("outflow", split=2), _edge("wall", split=4),
+                    _edge("outflow", split=1)],
+    "xperiodic": [_edge("periodic"), _edge("periodic"), _edge("wall"), _edge("outflow")],
+}
+
+SIZES = [(77, 13), (64, 3), (1, 5), (130, 1), (200, 70), (3, 2)]
+
+
+def _smooth_cfg(nx, ny, edges, seed=5, tau=1.0, beta=0.25):
+    cfg = P.periodic_smooth(nx=nx, ny=ny, seed=seed)
+    cfg["edges"] = edges
+    cfg["tau"], cfg["beta"] = tau, beta
+    return cfg
+
+
+@pytest.mark.parametrize("bcs", list(BC_SETS))
+@pytest.mark.parametrize("size", SIZES, ids=lambda s: "%dx%d" % s)
+def test_boundary_matrix_fp64(bcs, size):
+    nx, ny = size
+    cfg = _smooth_cfg(nx, ny, BC_SETS[bcs])
+    say("case", bcs, nx, ny)
+    g, f = gpu_run(cfg, 15, "f64")
+    got, _ = gpu_fields(g, f, "f64")
+    want, _ = oracle_run("bc-%s-%dx%d" % (bcs, nx, ny), cfg, 15)
+    compare_fields(got, want, 1e-12)
+
+
+@pytest.mark.parametrize("tau,beta", [(2.0, 0.25), (0.8, 0.0), (1.0, 0.5)])
+def test_tau_beta_variants(tau, beta):
+    cfg = _smooth_cfg(90, 21, BC_SETS["mixed_split"], tau=tau, beta=beta)
+    say("case tau beta", tau, beta)
+    g, f = gpu_run(cfg, 25, "f64")
+    got, _ = gpu_fields(g, f, "f64")
+    want, _ = oracle_run("tb-%g-%g" % (tau, beta), cfg, 25)
+    compare_fields(got, want, 1e-12)
+
+
+# ------------------------------------------------------------------ bitwise properties
+
+TILES = [(64, 1), (64, 5), (128, 16), (256, 32), (256, 240), (128, 3)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_every_launch_shape_is_bitwise_identical(prec):
+    cfg = P.double_mach(nx=333, ny=77)
+    say("case tiles", prec)
+    ref = None
+    for tile in TILES:
+        g, f = gpu_run(cfg, 20, prec, tile=tile)
+        a = f[:, :, :g.nx].clone()
+        if ref is None:
+            ref = a
+        else:
+            assert torch.equal(a, ref), tile
+    # graph replay of the same loop
+    g, f = gpu_run(cfg, 20, prec, use_graph=True)
+    assert torch.equal(f[:, :, :g.nx], ref)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_y_uniform_data_stay_bitwise_y_uniform(prec):
+    """ny = 4 periodic rows with the 1000:1 data: every row must stay identical."""
+    cfg = P.ratio1000()
+    say("case y-uniform", prec)
+    g, f = gpu_run(cfg, 4000, prec)
+    a = f[:, :, :g.nx]
+    for y in range(1, g.ny):
+        assert torch.equal(a[:, y], a[:, 0]), y
+
+
+def test_graph_replay_is_repeatable():
+    lb = _lb()
+    cfg = P.double_mach(nx=200, ny=50)
+    g, f0 = gpu_run(cfg, 0, "f64")
+    s = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            fa = f0.clone()
+            fb = torch.empty_like(fa)
+            r = lb.run(g, fa, fb, 10, prec="f64", use_graph=True)
+            torch.cuda.synchronize()
+            outs.append(r.clone())
+    g2, direct = gpu_run(cfg, 10, "f64")
+    for o in outs:
+        assert torch.equal(o[:, :, :g.nx], direct[:, :, :g.nx])
+
+
+# ------------------------------------------------------------------ invariants, moments, init
+
+def test_conservation_on_periodic_grid():
+    lb = _lb()
+    cfg = P.periodic_smooth(nx=256, ny=192)
+    g, f = gpu_run(cfg, 0, "f64")
+    t0 = lb.invariants(g, f).cpu()
+    pb = scheme.Problem.from_dict(cfg)
+    fo = scheme.init(pb, *P.init_fields(cfg))
+    tot = [float(q.sum()) for q in kt.conserved(fo, pb.c1, pb.c2, pb.eta0)]
+    for a, b in zip(t0.tolist(), tot):
+        assert abs(a - b) <= 1e-12 * max(abs(b), abs(tot[0]))
+    g, f = gpu_run(cfg, 1000, "f64")
+    t1 = lb.invariants(g, f).cpu()
+    scale = [abs(tot[0]), abs(tot[0]) * pb.c1, abs(tot[0]) * pb.c1, abs(tot[3])]
+    for a, b, s in zip(t0.tolist(), t1.tolist(), scale):
+        assert abs(a - b) / s < 1e-12, (a, b)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_moments_and_init_match_oracle(prec):
+    lb = _lb()
+    cfg = P.periodic_smooth(nx=150, ny=37)
+    g = lb.Grid.from_workload(cfg)
+    fields = [torch.tensor(np.ascontiguousarray(a), dtype=F64) for a in P.init_fields(cfg)]
+    f = lb.init(g, *[t.to(DEV) for t in fields], prec=prec)
+    pb = scheme.Problem.from_dict(cfg)
+    fo = scheme.init(pb, *fields)
+    tol = 1e-14 if prec == "f64" else 6e-8
+    got = lb.interior(g, f).cpu().to(F64)
+    assert float(((got - fo).abs() / fo.abs().max()).max()) < tol
+    # moments of a raw (non-equilibrium) array
+    raw = P.random_distributions(g.nx, g.ny, seed=11)
+    buf = lb.empty(g, prec, DEV)
+    buf.zero_()
+    buf[:, :, :g.nx] = torch.tensor(raw, dtype=buf.dtype)
+    r, ux, uy, T, flags = lb.moments(g, buf, prec=prec)
+    want = kt.moments(buf[:, :, :g.nx].cpu().to(F64), pb.c1, pb.c2, pb.eta0, pb.gamma)
+    compare_fields((r, ux, uy, T), want, 1e-14)
+    assert int(flags[0].cpu()) == 0
+
+
+def test_flags_report_nonfinite_and_nonpositive():
+    lb = _lb()
+    cfg = P.periodic_smooth(nx=100, ny=10)
+    g, f = gpu_run(cfg, 0, "f64")
+    f[0, 2, 5] = float("nan")
+    f[0, 3, 7] = float("inf")
+    f[:, 4, 9] = -1.0                    # rho < 0 at one site
+    f[:, 6, 11] = 0.0
+    f[0, 6, 11] = 1.0                    # only the rest particle: T = (eta0^2/1)/b > 0
+    f[:, 7, 12] = 0.0
+    f[3, 7, 12] = 1.0                    # one fast particle: T = (c1^2 - c1^2)/b = 0
+    r, ux, uy, T, flags = lb.moments(g, f)
+    fl = flags.cpu().tolist()
+    assert fl[0] == 1 | 2 | 4, fl
+    assert fl[1] == 2 and fl[2] == 1 and fl[3] == 1, fl
+
+
+# ------------------------------------------------------------------ full size, bench launch shape
+
+def test_roofline_grid_one_step_sampled_rows():
+    """8192 x 2048 (the benchmark workload), one step from a seeded random
+    non-equilibrium state in both precisions, rows sampled across every tile
+    boundary and both edges, against the oracle row by row."""
+    lb = _lb()
+    cfg = P.roofline_grid()
+    g = lb.Grid.from_workload(cfg)
+    pb = scheme.Problem.from_dict(cfg)
+    raw = P.random_distributions(g.nx, g.ny, seed=21)
+    rows = [0, 1, 31, 32, 33, 1023, 1024, 2015, 2046, 2047]
+    for prec in ("f64", "f32"):
+        say("case roofline", prec)
+        dt = torch.float64 if prec == "f64" else torch.float32
+        src = torch.tensor(raw, dtype=dt)
+        fa = lb.empty(g, prec, DEV)
+        fa[:, :, :g.nx] = src.to(DEV)
+        fb = lb.empty(g, prec, DEV)
+        lb.step(g, fa, fb, 0, prec=prec)
+        got = fb[:, rows, :g.nx].cpu().to(F64)
+        want = scheme.step_rows(pb, src.to(F64), 0, rows)
+        err = float(((got - want).abs() / want.abs().max()).max())
+        say("roofline", prec, "max rel err", err)
+        tol = 1e-13 if prec == "f64" else 1.2e-7
+        assert err < tol
+        del fa, fb
+        torch.cuda.empty_cache()
+
+
+def test_uniform_inflow_is_stationary():
+    lb = _lb()
+    st = (1.3, 0.7, -0.4, 0.9)
+    cfg = P.periodic_smooth(nx=130, ny=40)
+    cfg["edges"] = [{"kind": "inflow", "a": st} for _ in range(4)]
+    shape = (cfg["ny"], cfg["nx"])
+    fields = [np.full(shape, v) for v in st]
+    g, f0 = gpu_run(cfg, 0, "f64", fields=fields)
+    f0 = f0.clone()
+    g, f = gpu_run(cfg, 50, "f64", fields=fields)
+    a, b = lb.interior(g, f), lb.interior(g, f0)
+    assert float(((a - b).abs() / b.abs().max()).max()) < 1e-14
