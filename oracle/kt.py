@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import math
 
+import mpmath
 import torch
 
 F64 = torch.float64
@@ -25,17 +26,30 @@ F64 = torch.float64
 def velocities(c1: float, c2: float) -> torch.Tensor:
     """(9, 2) discrete velocities of Eq. (e14), diagonal group read as (cos, sin).
 
-    Components that are zero in exact arithmetic (cos(pi/2) etc.) are set to 0.
+    Each component c cos(theta), c sin(theta) is evaluated in 40-digit
+    arithmetic and rounded once to float64, so the set keeps its exact
+    symmetries (|v_x| = |v_y| on the diagonals, zeros exactly zero); float64
+    trig of the large angles pi (i+1)/2 would be off by several ulps.
     """
-    v = torch.zeros(9, 2, dtype=F64)
-    for i in range(1, 5):
-        th = math.pi * (i + 1) / 2.0
-        v[i, 0], v[i, 1] = c1 * math.cos(th), c1 * math.sin(th)
-    for i in range(5, 9):
-        th = math.pi * ((i + 1) / 2.0 + 0.25)
-        v[i, 0], v[i, 1] = c2 * math.cos(th), c2 * math.sin(th)
-    v[v.abs() < 1e-12 * max(c1, c2)] = 0.0
+    with mpmath.workdps(40):
+        v = torch.zeros(9, 2, dtype=F64)
+        for i in range(1, 5):
+            th = mpmath.pi * mpmath.mpf(i + 1) / 2
+            v[i, 0], v[i, 1] = float(c1 * mpmath.cos(th)), float(c1 * mpmath.sin(th))
+        for i in range(5, 9):
+            th = mpmath.pi * (mpmath.mpf(i + 1) / 2 + mpmath.mpf(1) / 4)
+            v[i, 0], v[i, 1] = float(c2 * mpmath.cos(th)), float(c2 * mpmath.sin(th))
+    v[v.abs() < 1e-30 * max(c1, c2)] = 0.0
     return v
+
+
+def energy_weights(c1: float, c2: float, eta0: float) -> torch.Tensor:
+    """|v_i|^2 + eta_i^2 of Eq. (e7): eta0^2, c1^2 (i = 1..4), c2^2 (i = 5..8).
+
+    |v_i| is c1 or c2 by Eq. (e14); the squares are rounded once, not rebuilt
+    from rounded components.
+    """
+    return torch.tensor([eta0 * eta0] + [c1 * c1] * 4 + [c2 * c2] * 4, dtype=F64)
 
 
 def etas(eta0: float) -> torch.Tensor:
@@ -91,7 +105,7 @@ def moments(f, c1, c2, eta0, gamma):
     rho = f.sum(0)
     jx = (f * v[:, 0].reshape(shape)).sum(0)
     jy = (f * v[:, 1].reshape(shape)).sum(0)
-    w = (v[:, 0] ** 2 + v[:, 1] ** 2 + et ** 2).reshape(shape)
+    w = energy_weights(c1, c2, eta0).reshape(shape)
     E = (f * w).sum(0)
     ux = jx / rho
     uy = jy / rho
@@ -105,7 +119,7 @@ def conserved(f, c1, c2, eta0):
     et = etas(eta0)
     shape = (9,) + (1,) * (f.dim() - 1)
     return (f.sum(0), (f * v[:, 0].reshape(shape)).sum(0), (f * v[:, 1].reshape(shape)).sum(0),
-            (f * (v[:, 0] ** 2 + v[:, 1] ** 2 + et ** 2).reshape(shape)).sum(0))
+            (f * energy_weights(c1, c2, eta0).reshape(shape)).sum(0))
 
 
 def mirror_permutation(c1: float, c2: float, axis: int):

@@ -36,12 +36,19 @@ struct KTConsts {
   double eta0sq, c1sq, c2sq;
   double inv_b;           // 1/b, b = 2/(gamma-1)
   double bval;            // b
-  // Eqs. (e17)-(e18) expanded as polynomials in T and usq = u.u:
-  //   A_0 = a0T T;  A_1..4 = a1c + a1T T + a1u usq;  A_5..8 = a5c + a5T T + a5u usq
-  //   B_1..4 = b1c + b1T T + b1u usq;  B_5..8 = b5c + b5T T + b5u usq;  D = d1, d5
-  double a0T, a1c, a1T, a1u, a5c, a5T, a5u;
-  double b1c, b1T, b1u, b5c, b5T, b5u;
+  // Eqs. (e17)-(e18) in the paper's grouping, one quotient per coefficient:
+  //   A_0 = a0T T
+  //   A_1..4 = (-c2^2 + k1T T + k1u usq) / k1d,  k1T = (b-2) c2^2/eta0^2 + 2, k1u = c2^2/c1^2, k1d = 4 (c1^2 - c2^2)
+  //   A_5..8 = (-c1^2 + k5T T + k5u usq) / k5d,  (c1 <-> c2)
+  //   B_1..4 = (-c2^2 + bT T + usq) / b1d,       bT = b + 2, b1d = 2 c1^2 (c1^2 - c2^2)
+  //   B_5..8 = (-c1^2 + bT T + usq) / b5d,       b5d = 2 c2^2 (c2^2 - c1^2)
+  //   D = d1 = 1/(2 c1^4), d5 = 1/(2 c2^4)
+  // with usq = u.u; r* are the rounded reciprocals of the divisors.
+  double a0T;
+  double k1u, k1T, k1d, r1d, k5u, k5T, k5d, r5d, bT, b1d, rb1d, b5d, rb5d;
   double d1, d5;
+  // derivatives for the adjoint: dA/dT, dA/dusq, dB/dT, dB/dusq per group
+  double a1T, a1u, a5T, a5u, b1T, b1u, b5T, b5u;
   // boundary edges x-, x+, y-, y+
   int32_t kind[4], split[4];
   double ga[4][9], gb[4][9];  // f^eq of edge states a and b
@@ -71,6 +78,16 @@ __host__ __device__ inline double vel_y(const KTConsts& K, int i) {
   }
 }
 
+// a / b given rb = 1/b rounded: one Newton-type correction of a * rb with the
+// exact FMA residual gives the correctly rounded quotient in all but rare
+// cases (Markstein), and never a systematic bias, for three operations
+// instead of a full division sequence.
+__host__ __device__ __forceinline__ double div_cr(double a, double b, double rb) {
+  const double q = a * rb;
+  const double r = fma(-q, b, a);
+  return fma(r, rb, q);
+}
+
 // Macroscopic fields, Eqs. (e4), (e5), (e7): rho, u = j/rho, T = (E/rho - u.u)/b.
 struct Prim { double rho, ux, uy, T, rinv, usq; };
 
@@ -84,10 +101,10 @@ __host__ __device__ inline Prim moments9(const KTConsts& K, const double f[9]) {
   Prim P;
   P.rho = rho;
   P.rinv = 1.0 / rho;
-  P.ux = jx * P.rinv;
-  P.uy = jy * P.rinv;
+  P.ux = div_cr(jx, rho, P.rinv);
+  P.uy = div_cr(jy, rho, P.rinv);
   P.usq = fma(P.ux, P.ux, P.uy * P.uy);
-  P.T = fma(E, P.rinv, -P.usq) * K.inv_b;
+  P.T = div_cr(div_cr(E, rho, P.rinv) - P.usq, K.bval, K.inv_b);
   return P;
 }
 
@@ -97,10 +114,10 @@ struct Coef { double A0, A1, A5, B1, B5; };
 __host__ __device__ inline Coef coef(const KTConsts& K, double T, double usq) {
   Coef C;
   C.A0 = K.a0T * T;
-  C.A1 = fma(K.a1u, usq, fma(K.a1T, T, K.a1c));
-  C.A5 = fma(K.a5u, usq, fma(K.a5T, T, K.a5c));
-  C.B1 = fma(K.b1u, usq, fma(K.b1T, T, K.b1c));
-  C.B5 = fma(K.b5u, usq, fma(K.b5T, T, K.b5c));
+  C.A1 = div_cr(fma(K.k1u, usq, fma(K.k1T, T, -K.c2sq)), K.k1d, K.r1d);
+  C.A5 = div_cr(fma(K.k5u, usq, fma(K.k5T, T, -K.c1sq)), K.k5d, K.r5d);
+  C.B1 = div_cr(fma(K.bT, T, usq) - K.c2sq, K.b1d, K.rb1d);
+  C.B5 = div_cr(fma(K.bT, T, usq) - K.c1sq, K.b5d, K.rb5d);
   return C;
 }
 

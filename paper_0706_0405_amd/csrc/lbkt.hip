@@ -126,7 +126,8 @@ static void build_consts(const lb_grid* g, KTConsts* K) {
   const double c1 = g->c1, c2 = g->c2, eta0 = g->eta0;
   const double b = 2.0 / (g->gamma - 1.0);
   K->c1 = c1;
-  K->s = c2 * std::sqrt(0.5);
+  // c2 cos(pi/4) rounded once to double (extended-precision product on the host)
+  K->s = (double)((long double)c2 * sqrtl(0.5L));
   K->eta0sq = eta0 * eta0;
   K->c1sq = c1 * c1;
   K->c2sq = c2 * c2;
@@ -136,19 +137,29 @@ static void build_consts(const lb_grid* g, KTConsts* K) {
   const double c1s = c1 * c1, c2s = c2 * c2, e2 = eta0 * eta0;
   // Eq. (e17), A_0 read as (b-2) T / eta0^2
   K->a0T = (b - 2.0) / e2;
-  K->a1c = -c2s / (4.0 * (c1s - c2s));
-  K->a1T = ((b - 2.0) * c2s / e2 + 2.0) / (4.0 * (c1s - c2s));
-  K->a1u = (c2s / c1s) / (4.0 * (c1s - c2s));
-  K->a5c = -c1s / (4.0 * (c2s - c1s));
-  K->a5T = ((b - 2.0) * c1s / e2 + 2.0) / (4.0 * (c2s - c1s));
-  K->a5u = (c1s / c2s) / (4.0 * (c2s - c1s));
+  K->k1u = c2s / c1s;
+  K->k1T = (b - 2.0) * c2s / e2 + 2.0;
+  K->k1d = 4.0 * (c1s - c2s);
+  K->r1d = 1.0 / K->k1d;
+  K->k5u = c1s / c2s;
+  K->k5T = (b - 2.0) * c1s / e2 + 2.0;
+  K->k5d = 4.0 * (c2s - c1s);
+  K->r5d = 1.0 / K->k5d;
   // Eq. (e18)
-  K->b1c = -c2s / (2.0 * c1s * (c1s - c2s));
-  K->b1T = (b + 2.0) / (2.0 * c1s * (c1s - c2s));
-  K->b1u = 1.0 / (2.0 * c1s * (c1s - c2s));
-  K->b5c = -c1s / (2.0 * c2s * (c2s - c1s));
-  K->b5T = (b + 2.0) / (2.0 * c2s * (c2s - c1s));
-  K->b5u = 1.0 / (2.0 * c2s * (c2s - c1s));
+  K->bT = b + 2.0;
+  K->b1d = 2.0 * c1s * (c1s - c2s);
+  K->rb1d = 1.0 / K->b1d;
+  K->b5d = 2.0 * c2s * (c2s - c1s);
+  K->rb5d = 1.0 / K->b5d;
+  // partial derivatives of A and B (adjoint only)
+  K->a1T = K->k1T / K->k1d;
+  K->a1u = K->k1u / K->k1d;
+  K->a5T = K->k5T / K->k5d;
+  K->a5u = K->k5u / K->k5d;
+  K->b1T = K->bT / K->b1d;
+  K->b1u = 1.0 / K->b1d;
+  K->b5T = K->bT / K->b5d;
+  K->b5u = 1.0 / K->b5d;
   K->d1 = 1.0 / (2.0 * c1s * c1s);
   K->d5 = 1.0 / (2.0 * c2s * c2s);
   // Linear stencil: Eqs. (SEC-VON-2a/2b) for the convection, central second

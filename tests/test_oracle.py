@@ -10,6 +10,8 @@ the paper's qualitative stability claims, and exact Riemann solutions.
 import math
 import os
 
+import mpmath
+
 import pytest
 import torch
 
@@ -45,6 +47,10 @@ def test_velocity_set_geometry():
     # the printed (cos, cos) form would make velocities 5..8 collinear with (1,1)
     d = torch.cdist(v, v) + torch.eye(9, dtype=F64)
     assert d.min() > 0.5
+    # exact symmetry of the set: every diagonal component is +-RN(c2/sqrt(2))
+    mags = v[5:].abs().flatten().unique()
+    assert mags.numel() == 1 and float(mags[0]) == float(mpmath.mpf(c2) / mpmath.sqrt(2))
+    assert v[1:5].abs().sum(1).eq(c1).all()
 
 
 @pytest.mark.parametrize("c1,c2,eta0,gamma", PARAM_SETS)
