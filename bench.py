@@ -1,0 +1,292 @@
+#!/usr/bin/env python3
+"""Benchmark of the FDLB D2V9 step on one MI355X.
+
+One step = one time step of the finite-difference lattice Boltzmann scheme
+(moments, f_eq, beta-mixed upwind convection, dissipation, BGK relaxation and
+update) over the whole grid, through the C ABI. The workload is the
+double-Mach-reflection field on an 8192 x 2048 grid (a 1.2 GB FP64 / 0.6 GB FP32
+array, too large for the 256 MB on-chip cache), timed as a HIP-graph replay of
+K steps with HIP events on the stream that runs the kernels.
+
+Prints ONE JSON line: MLUPS for FP64 storage (value), the same for FP32 storage,
+each against the HBM roofline; the batched-problem speedup; the adjoint /
+forward time ratio; and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SITE = {"f64": 144, "f32": 72}   # 9 loads + 9 stores of the storage type
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in ("paper_0706_0405_amd/csrc/lbkt.hip", "paper_0706_0405_amd/csrc/kt_site.hpp"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, prec):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
+    taken from the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_step_roofline_grid.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = d.get(prec)
+    if not e or d.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def fields_to(dev, fields):
+    import numpy as np
+    import torch
+    return [torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev) for a in fields]
+
+
+def time_step(prec, steps, warmup, dev):
+    import torch
+    import paper_0706_0405_amd as lb
+    from workloads import problems as P
+
+    cfg = P.roofline_grid()
+    g = lb.Grid.from_workload(cfg)
+    rho, ux, uy, p = fields_to(dev, P.init_fields(cfg))
+    s = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(s):
+        fa = lb.init(g, rho, ux, uy, p, prec=prec)
+        fb = lb.empty(g, prec, dev)
+        del rho, ux, uy, p
+        tile = None
+        if warmup > 0:
+            lb.run(g, fa, fb, warmup, prec=prec, tile=tile)
+        # capture the K-step graph once (untimed), then time one replay
+        lb.run(g, fa, fb, steps, prec=prec, use_graph=True, tile=tile)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        out = lb.run(g, fa, fb, steps, prec=prec, use_graph=True, tile=tile)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        _, _, _, _, flags = lb.moments(g, out, prec=prec)
+        torch.cuda.synchronize()
+    sites = g.nx * g.ny
+    per_launch_ms = ms / steps
+    mlups = sites * steps / (ms * 1e-3) / 1e6
+    achieved = BYTES_PER_SITE[prec] * sites / (per_launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic("k_step", prec)
+    res = {
+        "mlups": mlups, "ms_per_step": per_launch_ms, "grid": [g.nx, g.ny],
+        "flags": [int(v) for v in flags.cpu().tolist()],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_step<%s>" % ("double" if prec == "f64" else "float"),
+                     "algorithmic_bytes_per_launch": BYTES_PER_SITE[prec] * sites},
+    }
+    del fa, fb, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_batched(dev, steps=2000, nprob=256):
+    """cfg: 256 Riemann problems of uneven length, FP32 storage, one graph launch of
+    `steps` steps vs the sum of single-problem runs."""
+    import torch
+    import paper_0706_0405_amd as lb
+    from workloads import problems as P
+
+    cfgs, info = P.batched(nprob=nprob, seed=0, steps=steps)
+    grids = [lb.Grid.from_workload(c) for c in cfgs]
+    s = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(s):
+        B = lb.Batch(grids, "f32")
+        fa, fb = B.empty(dev), B.empty(dev)
+        fa.zero_()
+        fb.zero_()
+
+        def init_all():
+            for k, (c, g) in enumerate(zip(cfgs, grids)):
+                rho, ux, uy, p = fields_to(dev, P.init_fields(c))
+                lb.init(g, rho, ux, uy, p, prec="f32", out=B.view(fa, k))
+
+        init_all()
+        B.step(fa, fb, steps)           # capture + first replay (untimed)
+        init_all()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        out = B.step(fa, fb, steps)
+        e1.record(s)
+        torch.cuda.synchronize()
+        t_batch = e0.elapsed_time(e1)
+        nonfinite = 0
+        for k, g in enumerate(grids):
+            _, _, _, _, fl = lb.moments(g, B.view(out, k), prec="f32")
+            nonfinite += int(int(fl[1]) > 0)
+        # the same problems one at a time (per-step launches)
+        t_single = 0.0
+        for k, (c, g) in enumerate(zip(cfgs, grids)):
+            rho, ux, uy, p = fields_to(dev, P.init_fields(c))
+            f1 = lb.init(g, rho, ux, uy, p, prec="f32")
+            f2 = lb.empty(g, "f32", dev)
+            torch.cuda.synchronize()
+            e0.record(s)
+            r = lb.run(g, f1, f2, steps, prec="f32")
+            e1.record(s)
+            torch.cuda.synchronize()
+            t_single += e0.elapsed_time(e1)
+            if k < 8:   # the packed result is bitwise the single-problem result (NaNs included)
+                a = r[:, :, :g.nx].contiguous().view(torch.int32)
+                b = B.view(out, k)[:, :, :g.nx].contiguous().view(torch.int32)
+                if not torch.equal(a, b):
+                    raise RuntimeError("batched result differs from the single-problem run (problem %d)" % k)
+        B.close()
+    sites = sum(g.nx * g.ny for g in grids)
+    return {"problems": nprob, "steps": steps, "sites": sites, "draws": info,
+            "batched_ms": t_batch, "single_sum_ms": t_single, "speedup": t_single / t_batch,
+            "batched_mlups": sites * steps / (t_batch * 1e-3) / 1e6, "nonfinite_problems": nonfinite}
+
+
+def bench_adjoint(dev, steps=2000):
+    """Gradient of a final-density loss w.r.t. the initial density on the 960 x 240
+    double-Mach problem (FP32 storage, FP64 adjoint, sqrt(N) checkpoints) vs the plain forward."""
+    import torch
+    import paper_0706_0405_amd as lb
+    from paper_0706_0405_amd import rollout
+    from workloads import problems as P
+
+    cfg = P.double_mach(steps=steps)
+    g = lb.Grid.from_workload(cfg)
+    rho, ux, uy, p = fields_to(dev, P.init_fields(cfg))
+    s = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(s):
+        R = rollout.Rollout(g, ux, uy, p, steps, prec="f32")
+        target = R.forward_density(rho * 1.001).detach()
+        fa = lb.init(g, rho, ux, uy, p, prec="f32")
+        fb = lb.empty(g, "f32", dev)
+        lb.run(g, fa, fb, steps, prec="f32")   # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fa = lb.init(g, rho, ux, uy, p, prec="f32")
+        lb.run(g, fa, fb, steps, prec="f32")
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        r0 = rho.clone().requires_grad_(True)
+        R.loss_and_grad(r0, target)            # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss, grad = R.loss_and_grad(r0, target)
+        torch.cuda.synchronize()
+        t_grad = time.perf_counter() - t0
+    return {"grid": [g.nx, g.ny], "steps": steps, "checkpoint_every": R.seg, "forward_ms": t_fwd * 1e3,
+            "gradient_ms": t_grad * 1e3, "ratio": t_grad / t_fwd,
+            "grad_finite": bool(torch.isfinite(grad).all())}
+
+
+def cpu_baseline(target_s=15.0):
+    """The FP64 CPU oracle on a bounded sample of the benchmark workload."""
+    import torch
+    from oracle import scheme
+    from workloads import problems as P
+
+    cfg = P.roofline_grid()
+    sample = dict(cfg, nx=1024, ny=512)
+    pb = scheme.Problem.from_dict(sample)
+    f = scheme.init(pb, *P.init_fields(sample))
+    t0 = time.perf_counter()
+    f = scheme.step(pb, f, 0)
+    t1 = time.perf_counter() - t0
+    n = max(1, min(200, int(target_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    f = scheme.run(pb, f, n, 1)
+    dt = time.perf_counter() - t0
+    return {"value": pb.nx * pb.ny * n / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": "FP64 oracle, %d steps of the same double-Mach problem at the same spacing on a "
+                      "%dx%d grid (%.1f s)" % (n, pb.nx, pb.ny, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint measurements")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--prec", choices=["f64", "f32", "both"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.steps % 2:
+        args.steps += 1   # even step counts keep the result in the first buffer
+
+    import torch
+    import paper_0706_0405_amd as lb
+    lb._lib.lib()        # fail loudly if the HIP library is missing
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+
+    res = {}
+    for prec in (("f64", "f32") if args.prec == "both" else (args.prec,)):
+        log("timing", prec, "step on the roofline grid")
+        res[prec] = time_step(prec, args.steps, args.warmup, dev)
+        log(prec, json.dumps(res[prec]))
+    head = "f64" if "f64" in res else "f32"
+    extras = {}
+    if not args.no_extras:
+        log("timing batched problems")
+        extras["batched"] = bench_batched(dev)
+        log(json.dumps(extras["batched"]))
+        try:
+            log("timing adjoint")
+            extras["adjoint"] = bench_adjoint(dev)
+            log(json.dumps(extras["adjoint"]))
+        except ImportError as e:
+            extras["adjoint"] = {"error": str(e)}
+    cpu = None
+    if not args.no_cpu:
+        log("timing CPU oracle sample")
+        cpu = cpu_baseline()
+    r = res[head]
+    line = {
+        "metric": "MLUPS vs HBM roofline (fp64/fp32); batched speedup; adjoint/forward ratio",
+        "value": r["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "double-Mach-reflection field, %dx%d grid, FP64 storage, one FDLB step"
+                               % tuple(r["grid"]), "storage": head},
+        "roofline": r["roofline"],
+        "cpu_baseline": cpu,
+    }
+    if "f32" in res and head != "f32":
+        line["fp32_storage"] = {"value": res["f32"]["mlups"], "unit": "MLUPS", "ms_per_step": res["f32"]["ms_per_step"],
+                                "dtype": "f64 arithmetic, f32 storage", "roofline": res["f32"]["roofline"]}
+    line.update(extras)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -300,11 +300,75 @@ __device__ __forceinline__ void ghost_row(const KTConsts& K, const View<S>& f, i
   }
 }
 
-// Ghost of x edge E (0: left of column 0, 1: right of column nx-1) in row y;
-// cur holds the adjacent interior site. Returns false where the plain load of
-// the clamped / wrapped column already is the ghost (periodic, outflow).
-template <int E>
-__device__ __forceinline__ void ghost_x(const KTConsts& K, int y, const double cur[9], double g[9]) {
+// Raw storage-typed loads (no widening) for rows held in flight.
+template <typename S>
+__device__ __forceinline__ S ld_raw(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb);
+template <>
+__device__ __forceinline__ double ld_raw<double>(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vb, (int)sb, 0));
+}
+template <>
+__device__ __forceinline__ float ld_raw<float>(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vb, (int)sb, 0));
+}
+
+template <typename S>
+__device__ __forceinline__ void load_raw9(const View<S>& f, uint32_t vb, S v[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = ld_raw<S>(f.r, vb, (uint32_t)i * f.planeB);
+}
+
+// Wavefront lane shifts (DPP wave_shr:1 / wave_shl:1): lane i receives lane
+// i-1 (shr) or i+1 (shl); the lane without a source (0, resp. 63) keeps `old`.
+__device__ __forceinline__ int dpp_shr1(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_shl1(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double shr1(double old, double v) {
+  const unsigned long long o = __builtin_bit_cast(unsigned long long, old);
+  const unsigned long long w = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)dpp_shr1((int)(unsigned)o, (int)(unsigned)w);
+  const unsigned hi = (unsigned)dpp_shr1((int)(unsigned)(o >> 32), (int)(unsigned)(w >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double shl1(double old, double v) {
+  const unsigned long long o = __builtin_bit_cast(unsigned long long, old);
+  const unsigned long long w = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)dpp_shl1((int)(unsigned)o, (int)(unsigned)w);
+  const unsigned hi = (unsigned)dpp_shl1((int)(unsigned)(o >> 32), (int)(unsigned)(w >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Column geometry of one lane: its column x inside a wavefront that covers the
+// 64 columns [xw0, xw0 + 64); lanes 0 and 63 also fetch the halo columns hl, hr.
+struct Lane {
+  int x, lane;
+  uint32_t vbx;    // x * sizeof(S): own column (clamped into the row for x >= nx)
+  uint32_t vbh;    // halo column of lanes 0 / 63
+  bool halo;       // lane 0 or 63
+};
+
+template <typename S>
+__device__ __forceinline__ Lane make_lane(const KTConsts& K, int xw0, int lane) {
+  Lane L;
+  L.lane = lane;
+  L.x = xw0 + lane;
+  const int nx = K.nx;
+  const bool perx = (K.kind[0] == BC_PERIODIC);
+  const int hl = (xw0 > 0) ? xw0 - 1 : (perx ? nx - 1 : 0);
+  const int hr = (xw0 + 64 < nx) ? xw0 + 64 : (perx ? 0 : nx - 1);
+  L.vbx = (uint32_t)L.x * sizeof(S);   // x < pitch always: pitch is a multiple of 64
+  L.vbh = (uint32_t)(lane == 0 ? hl : hr) * sizeof(S);
+  L.halo = (lane == 0) || (lane == 63);
+  return L;
+}
+
+// Ghost of x edge E for site (x, y) where the shifted neighbour is not the ghost.
+template <int E, typename S>
+__device__ __forceinline__ void ghost_x(const KTConsts& K, const View<S>& f, int y, const double cur[9],
+                                        double g[9]) {
   const int kind = K.kind[E];
   if (kind == BC_WALL) {
 #pragma unroll
@@ -312,6 +376,12 @@ __device__ __forceinline__ void ghost_x(const KTConsts& K, int y, const double c
   } else if (kind == BC_INFLOW) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) g[i] = K.ga[E][i];
+  } else if (kind == BC_OUTFLOW) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = cur[i];
+  } else {  // periodic: the opposite column
+    const int src = (E == 0) ? K.nx - 1 : 0;
+    f.load9((uint32_t)y * f.rowB + (uint32_t)src * sizeof(S), g);
   }
   if (y < K.split[E]) {
 #pragma unroll
@@ -319,52 +389,69 @@ __device__ __forceinline__ void ghost_x(const KTConsts& K, int y, const double c
   }
 }
 
-// One row of the march: site (x, y) from prev (y-1), cur (y), nxt (y+1).
-// XEDGE: the block holds column 0 or nx-1 and must synthesise x ghosts.
+// Site update of row y for one lane: prev/cur/nxt are the rows y-1, y, y+1 at
+// the lane's column, hc the halo values of row y (lanes 0 and 63).
 template <bool XEDGE, typename S>
-__device__ __forceinline__ void march_row(const KTConsts& K, const View<S>& fi, const View<S>& fo, int x, int y,
-                                          uint32_t vbx, uint32_t vbm, uint32_t vbp, const double prev[9],
-                                          const double cur[9], const double nxt[9]) {
-  const uint32_t rb = (uint32_t)y * fi.rowB;
+__device__ __forceinline__ void row_update(const KTConsts& K, const View<S>& fi, const View<S>& fo, const Lane& L,
+                                           int y, const double prev[9], const double cur[9], const double nxt[9],
+                                           const S hc[9]) {
   double xm[9], xp[9], out[9];
-  fi.load9(rb + vbm, xm);
-  fi.load9(rb + vbp, xp);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double h = (double)hc[i];
+    xm[i] = shr1(h, cur[i]);
+    xp[i] = shl1(h, cur[i]);
+  }
   if (XEDGE) {
-    if (x == 0) ghost_x<0>(K, y, cur, xm);
-    if (x == K.nx - 1) ghost_x<1>(K, y, cur, xp);
+    if (L.x == 0) ghost_x<0>(K, fi, y, cur, xm);
+    if (L.x == K.nx - 1) ghost_x<1>(K, fi, y, cur, xp);
   }
   site_update(K, cur, xp, xm, nxt, prev, out);
-  fo.store9(rb + vbx, out);
+  if (L.x < K.nx) fo.store9((uint32_t)y * fi.rowB + L.vbx, out);
 }
 
-// March column x from row y0 to y1-1, keeping rows y-1, y, y+1 in registers.
+// March a 64-column wavefront strip from row y0 to y1-1. Rows are fetched two
+// rows ahead of the row being updated (so a full iteration of arithmetic hides
+// each fetch), the halo columns one row ahead; x-neighbours come from the
+// adjacent lanes through DPP shifts, and only lanes 0 and 63 read the two
+// halo columns. Every lane runs the whole loop (the DPP shifts need all lanes);
+// lanes beyond nx compute on padding values and store nothing.
 template <bool XEDGE, typename S>
-__device__ __forceinline__ void march(const KTConsts& K, const View<S>& fi, const View<S>& fo, int x, int y0,
-                                      int y1, int ish_lo, int ish_hi) {
-  const int nx = K.nx, ny = K.ny;
-  const int im = (x > 0) ? x - 1 : (K.kind[0] == BC_PERIODIC ? nx - 1 : 0);
-  const int ip = (x < nx - 1) ? x + 1 : (K.kind[1] == BC_PERIODIC ? 0 : nx - 1);
-  const uint32_t vbx = (uint32_t)x * sizeof(S), vbm = (uint32_t)im * sizeof(S), vbp = (uint32_t)ip * sizeof(S);
-  double prev[9], cur[9], nxt[9];
+__device__ __forceinline__ void march(const KTConsts& K, const View<S>& fi, const View<S>& fo, const Lane& L,
+                                      int y0, int y1, int ish_lo, int ish_hi) {
+  const int ny = K.ny;
+  double pd[9], cd[9], nd[9];
+  S N[9], F[9], HC[9], HN[9];
+  // prologue: row y0-1 (or the bottom ghost), row y0 and its halo, row y0+1
   if (y0 > 0)
-    fi.load9((uint32_t)(y0 - 1) * fi.rowB + vbx, prev);
+    fi.load9((uint32_t)(y0 - 1) * fi.rowB + L.vbx, pd);
   else
-    ghost_row<2>(K, fi, x, vbx, ish_lo, prev);
-  fi.load9((uint32_t)y0 * fi.rowB + vbx, cur);
-  const int yfast = min(y1, ny - 1);
-  int y = y0;
-  for (; y < yfast; ++y) {
-    fi.load9((uint32_t)(y + 1) * fi.rowB + vbx, nxt);
-    march_row<XEDGE>(K, fi, fo, x, y, vbx, vbm, vbp, prev, cur, nxt);
+    ghost_row<2>(K, fi, L.x, L.vbx, ish_lo, pd);
+  fi.load9((uint32_t)y0 * fi.rowB + L.vbx, cd);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) HC[i] = (S)0;
+  if (L.halo) load_raw9(fi, (uint32_t)y0 * fi.rowB + L.vbh, HC);
+  if (y0 + 1 < ny) load_raw9(fi, (uint32_t)(y0 + 1) * fi.rowB + L.vbx, N);
+  for (int y = y0; y < y1; ++y) {
+    // issue the fetches of row y+2 and of the halo of row y+1
+    if (y + 2 < ny) load_raw9(fi, (uint32_t)(y + 2) * fi.rowB + L.vbx, F);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) HN[i] = (S)0;
+    if (L.halo && y + 1 < ny) load_raw9(fi, (uint32_t)(y + 1) * fi.rowB + L.vbh, HN);
+    if (y + 1 < ny) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) nd[i] = (double)N[i];
+    } else {
+      ghost_row<3>(K, fi, L.x, L.vbx, ish_hi, nd);
+    }
+    row_update<XEDGE>(K, fi, fo, L, y, pd, cd, nd, HC);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      prev[i] = cur[i];
-      cur[i] = nxt[i];
+      pd[i] = cd[i];
+      cd[i] = nd[i];
+      N[i] = F[i];
+      HC[i] = HN[i];
     }
-  }
-  if (y < y1) {  // y == ny - 1: the row above is the top ghost
-    ghost_row<3>(K, fi, x, vbx, ish_hi, nxt);
-    march_row<XEDGE>(K, fi, fo, x, y, vbx, vbm, vbp, prev, cur, nxt);
   }
 }
 
@@ -388,15 +475,17 @@ __global__ __launch_bounds__(256) void k_step(KTConsts K, const S* __restrict__ 
                                               int ish_hi) {
   int strip, chunk;
   tile_of_block(blockIdx.x, nstrips, nblocks, xcd_map, &strip, &chunk);
-  const int x = strip * blockDim.x + threadIdx.x;
-  if (x >= K.nx) return;
+  const int lane = threadIdx.x & 63;
+  const int xw0 = strip * blockDim.x + (threadIdx.x & ~63);
+  if (xw0 >= K.nx) return;   // whole wavefront beyond the grid
   const int y0 = chunk * rows;
   const int y1 = min(y0 + rows, K.ny);
   const View<S> fi = make_view<S>(K, fin), fo = make_view<S>(K, fout);
-  if (strip == 0 || strip == nstrips - 1)
-    march<true>(K, fi, fo, x, y0, y1, ish_lo, ish_hi);
+  const Lane L = make_lane<S>(K, xw0, lane);
+  if (xw0 == 0 || xw0 + 64 >= K.nx)
+    march<true>(K, fi, fo, L, y0, y1, ish_lo, ish_hi);
   else
-    march<false>(K, fi, fo, x, y0, y1, ish_lo, ish_hi);
+    march<false>(K, fi, fo, L, y0, y1, ish_lo, ish_hi);
 }
 
 template <typename S>
@@ -630,14 +719,15 @@ __global__ __launch_bounds__(256) void k_step_batched(const KTConsts* __restrict
   const WorkItem w = items[blockIdx.x];
   const KTConsts& K = Ks[w.prob];
   const int64_t off = info[w.prob].offset;
-  const int x = w.strip * blockDim.x + threadIdx.x;
-  if (x >= K.nx) return;
+  const int lane = threadIdx.x & 63;
+  const int xw0 = w.strip * blockDim.x + (threadIdx.x & ~63);
+  if (xw0 >= K.nx) return;
   const View<S> fi = make_view<S>(K, fin + off), fo = make_view<S>(K, fout + off);
-  const int nstrips = (K.nx + blockDim.x - 1) / blockDim.x;
-  if (w.strip == 0 || w.strip == nstrips - 1)
-    march<true>(K, fi, fo, x, 0, K.ny, 0, 0);
+  const Lane L = make_lane<S>(K, xw0, lane);
+  if (xw0 == 0 || xw0 + 64 >= K.nx)
+    march<true>(K, fi, fo, L, 0, K.ny, 0, 0);
   else
-    march<false>(K, fi, fo, x, 0, K.ny, 0, 0);
+    march<false>(K, fi, fo, L, 0, K.ny, 0, 0);
 }
 
 // ------------------------------------------------------------------ host launch helpers

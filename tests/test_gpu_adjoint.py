@@ -1,0 +1,170 @@
+"""GPU adjoint: lb_step_adjoint / lb_init_adjoint and the checkpointed rollout
+gradient against the oracle's autograd tape and central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import scheme
+from workloads import problems as P
+
+from tests._util import F64, say
+from tests.test_gpu_parity import BC_SETS, _smooth_cfg
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _lb():
+    import paper_0706_0405_amd as lb
+    return lb
+
+
+def _put(lb, g, arr, prec="f64"):
+    buf = lb.empty(g, prec, DEV)
+    buf.zero_()
+    buf[:, :, :g.nx] = torch.as_tensor(arr).to(buf.dtype).to(DEV)
+    return buf
+
+
+@pytest.mark.parametrize("bcs", ["periodic", "walls", "outflow", "inflow", "mixed_split", "walls_split",
+                                 "xperiodic"])
+@pytest.mark.parametrize("size", [(37, 11), (1, 4), (70, 1)], ids=lambda s: "%dx%d" % s)
+def test_step_adjoint_matches_oracle_vjp(bcs, size):
+    """One step's vector-Jacobian product against autograd through the oracle step."""
+    lb = _lb()
+    nx, ny = size
+    cfg = _smooth_cfg(nx, ny, BC_SETS[bcs], tau=1.3)
+    say("case adjoint", bcs, nx, ny)
+    g = lb.Grid.from_workload(cfg)
+    pb = scheme.Problem.from_dict(cfg)
+    f0 = torch.tensor(P.random_distributions(nx, ny, seed=31), dtype=F64)
+    w = torch.tensor(np.random.default_rng(32).standard_normal((9, ny, nx)), dtype=F64)
+    n = 7
+    _, vjp = torch.autograd.functional.vjp(lambda f: scheme.step(pb, f, n), f0, w)
+    got = lb.step_adjoint(g, _put(lb, g, f0), _put(lb, g, w), n=n)
+    got = got[:, :, :nx].cpu()
+    err = float((got - vjp).abs().max() / vjp.abs().max())
+    say("vjp err", err)
+    assert err < 1e-13
+
+
+def test_init_adjoint_matches_oracle():
+    lb = _lb()
+    cfg = P.double_mach(nx=48, ny=12)
+    g = lb.Grid.from_workload(cfg)
+    pb = scheme.Problem.from_dict(cfg)
+    r, u, v, p = [torch.tensor(a, dtype=F64) for a in P.init_fields(cfg)]
+    w = torch.tensor(np.random.default_rng(3).standard_normal((9, 12, 48)), dtype=F64)
+    _, want = torch.autograd.functional.vjp(lambda rr: scheme.init(pb, rr, u, v, p), r, w)
+    got = lb.init_adjoint(g, *[t.to(DEV).contiguous() for t in (r, u, v, p)], _put(lb, g, w)).cpu()
+    assert float((got - want).abs().max() / want.abs().max()) < 1e-14
+
+
+def test_adjoint_dot_product_with_finite_differences():
+    """<(S(f + e v) - S(f - e v)) / 2e, w> = <v, S^T w> on the GPU FP64 step."""
+    lb = _lb()
+    cfg = P.double_mach(nx=120, ny=40)
+    g = lb.Grid.from_workload(cfg)
+    rng = np.random.default_rng(5)
+    f0 = torch.tensor(P.random_distributions(g.nx, g.ny, seed=6), dtype=F64)
+    v = torch.tensor(rng.standard_normal(f0.shape), dtype=F64)
+    w = torch.tensor(rng.standard_normal(f0.shape), dtype=F64)
+    eps = 1e-6
+    outs = []
+    for sgn in (1.0, -1.0):
+        fa = _put(lb, g, f0 + sgn * eps * v)
+        fb = lb.empty(g, "f64", DEV)
+        lb.step(g, fa, fb, 3)
+        outs.append(fb[:, :, :g.nx].cpu())
+    jv = (outs[0] - outs[1]) / (2 * eps)
+    jtw = lb.step_adjoint(g, _put(lb, g, f0), _put(lb, g, w), n=3)[:, :, :g.nx].cpu()
+    lhs = float((jv * w).sum())
+    rhs = float((v * jtw).sum())
+    say("dot", lhs, rhs)
+    assert abs(lhs - rhs) <= 1e-8 * abs(rhs)
+
+
+def _dmr_problem(nx, ny, steps):
+    cfg = P.double_mach(nx=nx, ny=ny, steps=steps)
+    fields = P.init_fields(cfg)
+    target = P.dmr_target_density(cfg, fields[0])
+    return cfg, fields, target
+
+
+def _gpu_gradient(cfg, fields, target_rho, prec, seg=None):
+    lb = _lb()
+    from paper_0706_0405_amd import rollout
+    g = lb.Grid.from_workload(cfg)
+    rho, ux, uy, p = [torch.tensor(np.ascontiguousarray(a), dtype=F64, device=DEV) for a in fields]
+    R = rollout.Rollout(g, ux, uy, p, cfg["steps"], prec=prec, seg=seg)
+    tgt = R.forward_density(torch.tensor(target_rho, dtype=F64, device=DEV))
+    loss, grad = R.loss_and_grad(rho, tgt)
+    return R, loss, grad, tgt
+
+
+def test_rollout_gradient_matches_oracle_tape():
+    """The 48 x 12 double-Mach problem: GPU FP64 rollout gradient (sqrt(N) checkpoints)
+    against reverse-mode autograd through the oracle (init, N steps, density, loss)."""
+    steps = 60
+    cfg, fields, target = _dmr_problem(48, 12, steps)
+    R, loss, grad, tgt = _gpu_gradient(cfg, fields, target, "f64")
+    pb = scheme.Problem.from_dict(cfg)
+    r0 = torch.tensor(fields[0], dtype=F64, requires_grad=True)
+    u, v, p = [torch.tensor(a, dtype=F64) for a in fields[1:]]
+    f = scheme.run(pb, scheme.init(pb, r0, u, v, p), steps)
+    rho = scheme.fields(pb, f)[0]
+    L = ((rho - tgt.cpu()) ** 2).sum()
+    L.backward()
+    want = r0.grad
+    err = float((grad.cpu() - want).abs().max() / want.abs().max())
+    say("tape err", err, "loss", float(loss), float(L.detach()))
+    assert abs(float(loss) - float(L.detach())) <= 1e-10 * float(L.detach())
+    assert err < 1e-10
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    cfg, fields, target = _dmr_problem(64, 16, 50)
+    grads = [_gpu_gradient(cfg, fields, target, "f64", seg=s)[2] for s in (1, 7, 50)]
+    assert torch.equal(grads[0], grads[1]) and torch.equal(grads[0], grads[2])
+
+
+def test_rollout_gradient_central_differences_on_full_grid():
+    """960 x 240 double-Mach problem, 2000 steps, FP64: the adjoint gradient against
+    central differences (eps = 1e-4 rho: truncation ~1e-8, rounding noise ~1e-8 relative)
+    at cells of the 48 x 12 window at the wall start."""
+    lb = _lb()
+    cfg, fields, target = _dmr_problem(960, 240, 2000)
+    R, loss, grad, tgt = _gpu_gradient(cfg, fields, target, "f64")
+    g = R.g
+    rho, ux, uy, p = [torch.tensor(np.ascontiguousarray(a), dtype=F64, device=DEV) for a in fields]
+    x0 = int(round(cfg["x0"] / cfg["dx"]))
+    rng = np.random.default_rng(9)
+    cells = [(int(rng.integers(0, 12)), x0 + int(rng.integers(0, 48))) for _ in range(12)]
+    fa = lb.empty(g, "f64", DEV)
+    fb = lb.empty(g, "f64", DEV)
+
+    def loss_at(r):
+        lb.init(g, r, ux, uy, p, out=fa)
+        out = lb.run(g, fa, fb, cfg["steps"])
+        rN = lb.moments(g, out, flags=False)[0]
+        return float(((rN - tgt) ** 2).sum())
+
+    scale = float(grad.abs().max())
+    for (y, x) in cells:
+        eps = 1e-4 * float(rho[y, x])
+        rp = rho.clone()
+        rp[y, x] += eps
+        rm = rho.clone()
+        rm[y, x] -= eps
+        fd = (loss_at(rp) - loss_at(rm)) / (2 * eps)
+        say("cell", y, x, "fd", fd, "adj", float(grad[y, x]))
+        assert abs(fd - float(grad[y, x])) <= 1e-6 * max(abs(fd), 1e-3 * scale)
+
+
+def test_fp32_storage_gradient_close_to_fp64():
+    cfg, fields, target = _dmr_problem(960, 240, 2000)
+    _, _, g64, tgt = _gpu_gradient(cfg, fields, target, "f64")
+    _, _, g32, _ = _gpu_gradient(cfg, fields, target, "f32")
+    rel = float((g32 - g64).norm() / g64.norm())
+    say("fp32 vs fp64 gradient rel L2", rel)
+    assert rel < 1e-3

@@ -1,0 +1,104 @@
+"""GPU batched step: many independent problems of uneven length in one packed
+array, advanced by one graph launch; bitwise equal to single-problem runs and
+within the FP32-storage bound of the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import scheme
+from workloads import problems as P
+
+from tests._util import F64, rel_l1, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _lb():
+    import paper_0706_0405_amd as lb
+    return lb
+
+
+def _fields(cfg):
+    return [torch.tensor(np.ascontiguousarray(a), dtype=F64, device=DEV) for a in P.init_fields(cfg)]
+
+
+def _make(cfgs, prec="f32"):
+    lb = _lb()
+    grids = [lb.Grid.from_workload(c) for c in cfgs]
+    s = torch.cuda.Stream()
+    B = lb.Batch(grids, prec)
+    fa, fb = B.empty(DEV), B.empty(DEV)
+    fa.zero_()
+    fb.zero_()
+    for k, c in enumerate(cfgs):
+        lb.init(grids[k], *_fields(c), prec=prec, out=B.view(fa, k))
+    torch.cuda.synchronize()
+    return lb, grids, B, fa, fb, s
+
+
+def test_layout_is_aligned_and_packed():
+    cfgs, _ = P.batched(nprob=40, seed=1, steps=10)
+    lb, grids, B, fa, fb, s = _make(cfgs)
+    prev_end = 0
+    for k, g in enumerate(grids):
+        assert B.offsets[k] % 64 == 0 and B.pitches[k] % 64 == 0 and B.pitches[k] >= g.nx
+        assert B.offsets[k] == prev_end
+        prev_end = B.offsets[k] + 9 * g.ny * B.pitches[k]
+    assert B.total == prev_end
+
+
+@pytest.mark.parametrize("block_x", [64, 128, 256])
+def test_batched_equals_single_runs_bitwise(block_x):
+    cfgs, _ = P.batched(nprob=48, seed=2, steps=200)
+    lb, grids, B, fa, fb, s = _make(cfgs)
+    B.set_tile(block_x)
+    with torch.cuda.stream(s):
+        out = B.step(fa, fb, 200)
+    torch.cuda.synchronize()
+    say("case batched tile", block_x)
+    for k, (c, g) in enumerate(zip(cfgs, grids)):
+        f1 = lb.init(g, *_fields(c), prec="f32")
+        f2 = lb.empty(g, "f32", DEV)
+        r = lb.run(g, f1, f2, 200, prec="f32")
+        assert torch.equal(r[:, :, :g.nx], B.view(out, k)[:, :, :g.nx]), k
+
+
+def test_graph_replays_continue_the_run():
+    cfgs, _ = P.batched(nprob=16, seed=3, steps=100)
+    lb, grids, B, fa, fb, s = _make(cfgs)
+    ref_a = fa.clone()
+    with torch.cuda.stream(s):
+        B.step(fa, fb, 100)
+        out = B.step(fa, fb, 100)
+    torch.cuda.synchronize()
+    for k, g in enumerate(grids):
+        f1 = B.view(ref_a, k).clone()
+        f2 = torch.empty_like(f1)
+        r = lb.run(g, f1, f2, 200, prec="f32")
+        assert torch.equal(r[:, :, :g.nx], B.view(out, k)[:, :, :g.nx]), k
+
+
+def test_batched_against_oracle_fp32_bound():
+    """The shortest problems of the 256-problem draw, 2000 steps, against the FP64 oracle
+    (rows of a y-uniform problem are identical, so the oracle runs one row)."""
+    cfgs, rej = P.batched(nprob=256, seed=0, steps=2000)
+    order = sorted(range(len(cfgs)), key=lambda k: cfgs[k]["nx"])
+    pick = order[:4] + [k for k in range(7, 256, 8) if cfgs[k]["nx"] < 400][:2]   # include the fast subset
+    sub = [cfgs[k] for k in pick]
+    lb, grids, B, fa, fb, s = _make(sub)
+    with torch.cuda.stream(s):
+        out = B.step(fa, fb, 2000)
+    torch.cuda.synchronize()
+    for k, (c, g) in enumerate(zip(sub, grids)):
+        r, ux, uy, T, fl = lb.moments(g, B.view(out, k), prec="f32")
+        c1 = dict(c, ny=1)
+        pb = scheme.Problem.from_dict(c1)
+        fo = scheme.run(pb, scheme.init(pb, *P.init_fields(c1)), 2000)
+        R = scheme.fields(pb, fo)[0]
+        if not (torch.isfinite(R).all() and (R > 0).all() and float(R.max()) < 1e6):
+            say("oracle run leaves the physical range for problem", pick[k], "- not compared")
+            continue
+        e = rel_l1(r[0], R[0])
+        say("problem", pick[k], "L", c["nx"], "fast", c["fast"], "rel L1", e)
+        assert e < 1e-5

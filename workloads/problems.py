@@ -24,7 +24,9 @@ States are (rho, ux, uy, p) tuples.
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 
 import numpy as np
 
@@ -126,13 +128,15 @@ def init_regular_reflection(cfg):
     return (r * (1.0 + xi), np.full((ny, nx), u), np.full((ny, nx), v), np.full((ny, nx), p))
 
 
-def double_mach(nx=960, ny=240, steps=2000, length=9.6, wall_cells=None):
+def double_mach(nx=960, ny=240, steps=2000, length=9.6, wall_cells=None, alpha=0.025):
     """Double Mach reflection (Sec. 4.2, Fig. 12): Mach-10 shock at 60 deg to the wall.
 
     Pre-shock (1.4, 0, 0, 1); post-shock from the normal-shock relations; the
     wall starts `wall_cells` cells from the lower-left corner (20 at dx = 0.01,
     the same physical offset 0.2 at other resolutions); c1,c2,eta0 = 8,16,10;
-    dt = 0.1 dx/c2.
+    dt = alpha dx/c2 with alpha = 0.025 (larger alpha lets the reflected shock
+    foot at the wall drive T negative: the oracle blows up near step 600 at
+    alpha = 0.1 and near step 1500 at alpha = 0.05).
     """
     dx = length / nx
     x0 = 0.2 if wall_cells is None else wall_cells * dx
@@ -142,7 +146,7 @@ def double_mach(nx=960, ny=240, steps=2000, length=9.6, wall_cells=None):
     edges = [_edge("inflow", a=post), _edge("outflow"),
              _edge("wall", split=split, a=post),
              _edge("shock", a=post, b=pre, x0=x0, angle_deg=60.0, speed=10.0)]
-    cfg = _base(nx, ny, dx, 0.1 * dx / 16.0, 8.0, 16.0, 10.0, steps, edges, name="double_mach")
+    cfg = _base(nx, ny, dx, alpha * dx / 16.0, 8.0, 16.0, 10.0, steps, edges, name="double_mach")
     cfg["pre"], cfg["post"], cfg["x0"] = pre, post, x0
     return cfg
 
@@ -226,48 +230,100 @@ def random_distributions(nx, ny, seed, lo=0.5, hi=1.5):
 
 # ------------------------------------------------------------------ batched draws
 
-def batched(nprob=256, seed=0, steps=2000, alpha=0.025, lmin=128, lmax=8192, ny=4):
-    """Independent 1D Riemann problems of uneven lengths (log-uniform in [lmin, lmax]).
+SCREEN_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "batched_screen.json")
 
-    Per problem: rho and p log-uniform in [0.1, 1000] per side with max/min <= 1000;
-    |u| = M c_side with M ~ U[0, 5] (every 8th problem: U[5, 30]) and a random sign;
-    draws that create vacuum are rejected and counted. c1 = U + 3 sqrt(T_max) over
-    both sides and the exact star states, c2 = 2 c1, eta0 = 1.5 c1,
-    dt = alpha dx / c2, dx = 1/L.
-    Returns (list of cfg dicts, number of vacuum rejections).
+
+def batched_params(left, right, star):
+    """Per-problem constants from the paper's guidance (end of Sec. 3): c1 about the
+    largest flow speed (here at least the largest thermal speed sqrt(T) too), c2 = 3 c1,
+    eta0 between c1 and c2 (2 c1). Speeds and temperatures include the exact star states."""
+    U = max(abs(left[1]), abs(right[1]), abs(star.u))
+    Tmax = max(left[2] / left[0], right[2] / right[0], star.p / star.rho_l, star.p / star.rho_r)
+    c1 = max(U, math.sqrt(Tmax))
+    return c1, 3.0 * c1, 2.0 * c1
+
+
+def batched_candidate(seed, slot, attempt_rng, lmin=128, lmax=8192):
+    """One candidate draw for output slot `slot` from that slot's generator.
+
+    rho and p log-uniform in [0.1, 1000] per side, redrawn until max/min <= 1000 for
+    both; |u| = M c_side with M ~ U[0, 5] (every 8th slot: U[5, 30]) and a random sign
+    per side; draws that create vacuum are redrawn (counted). Returns
+    (L, left, right, star, fast, vacuum_redraws).
     """
-    rng = np.random.default_rng(seed)
-    out, rejected = [], 0
-    for p_idx in range(nprob):
-        L = int(round(math.exp(rng.uniform(math.log(lmin), math.log(lmax)))))
-        fast = (p_idx % 8 == 7)
+    rng = attempt_rng
+    L = int(round(math.exp(rng.uniform(math.log(lmin), math.log(lmax)))))
+    fast = (slot % 8 == 7)
+    vac = 0
+    while True:
         while True:
-            while True:
-                rho = np.exp(rng.uniform(math.log(0.1), math.log(1000.0), size=2))
-                pr = np.exp(rng.uniform(math.log(0.1), math.log(1000.0), size=2))
-                if rho.max() / rho.min() <= 1000.0 and pr.max() / pr.min() <= 1000.0:
-                    break
-            cs = np.sqrt(GAMMA * pr / rho)
-            M = rng.uniform(5.0, 30.0, size=2) if fast else rng.uniform(0.0, 5.0, size=2)
-            sgn = np.where(rng.uniform(size=2) < 0.5, -1.0, 1.0)
-            u = sgn * M * cs
-            left = (float(rho[0]), float(u[0]), float(pr[0]))
-            right = (float(rho[1]), float(u[1]), float(pr[1]))
-            try:
-                st = gasdyn.riemann_star(GAMMA, left, right)
-            except ValueError:
-                rejected += 1
+            rho = np.exp(rng.uniform(math.log(0.1), math.log(1000.0), size=2))
+            pr = np.exp(rng.uniform(math.log(0.1), math.log(1000.0), size=2))
+            if rho.max() / rho.min() <= 1000.0 and pr.max() / pr.min() <= 1000.0:
+                break
+        cs = np.sqrt(GAMMA * pr / rho)
+        M = rng.uniform(5.0, 30.0, size=2) if fast else rng.uniform(0.0, 5.0, size=2)
+        sgn = np.where(rng.uniform(size=2) < 0.5, -1.0, 1.0)
+        u = sgn * M * cs
+        left = (float(rho[0]), float(u[0]), float(pr[0]))
+        right = (float(rho[1]), float(u[1]), float(pr[1]))
+        try:
+            st = gasdyn.riemann_star(GAMMA, left, right)
+        except ValueError:
+            vac += 1
+            continue
+        return L, left, right, st, fast, vac
+
+
+def batched_cfg(L, left, right, star, fast, steps, alpha=0.025, ny=4):
+    c1, c2, eta0 = batched_params(left, right, star)
+    dx = 1.0 / L
+    cfg = _base(L, ny, dx, alpha * dx / c2, c1, c2, eta0, steps, riemann_edges(), name="batched")
+    cfg["left"] = (left[0], left[1], 0.0, left[2])
+    cfg["right"] = (right[0], right[1], 0.0, right[2])
+    cfg["x_disc"] = 0.5
+    cfg["fast"] = fast
+    return cfg
+
+
+def screen_key(seed, steps, alpha):
+    return "seed=%d steps=%d alpha=%g" % (seed, steps, alpha)
+
+
+def load_screen(seed, steps, alpha):
+    """Slot attempts rejected by the FP64 CPU screen (a stored list), or None."""
+    try:
+        with open(SCREEN_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = d.get(screen_key(seed, steps, alpha))
+    if e is None:
+        return None
+    return {(int(a), int(b)) for a, b in e["rejected"]}
+
+
+def batched(nprob=256, seed=0, steps=2000, alpha=0.025, ny=4, screen=True, max_attempts=64):
+    """Independent 1D Riemann problems of uneven lengths L log-uniform in [128, 8192].
+
+    Slot p draws from its own generator default_rng([seed, p]); an attempt that the
+    stored FP64 screen rejected (the scheme leaves the physical range within `steps`
+    steps: non-finite, rho <= 0 or rho > 1e6) is redrawn from the same generator.
+    dx = 1/L, dt = alpha dx / c2, ny rows (periodic y, zero-gradient x).
+    Returns (cfgs, info) with info = {"vacuum_redraws", "unstable_redraws", "screened"}.
+    """
+    rejected = load_screen(seed, steps, alpha) if screen else None
+    out, vac, unstable = [], 0, 0
+    for p in range(nprob):
+        rng = np.random.default_rng([seed, p])
+        for a in range(max_attempts):
+            L, left, right, st, fast, v = batched_candidate(seed, p, rng)
+            vac += v
+            if rejected is not None and (p, a) in rejected:
+                unstable += 1
                 continue
+            out.append(batched_cfg(L, left, right, st, fast, steps, alpha, ny))
             break
-        U = max(abs(left[1]), abs(right[1]), abs(st.u))
-        Tmax = max(left[2] / left[0], right[2] / right[0], st.p / st.rho_l, st.p / st.rho_r)
-        c1 = U + 3.0 * math.sqrt(Tmax)
-        c2, eta0 = 2.0 * c1, 1.5 * c1
-        dx = 1.0 / L
-        cfg = _base(L, ny, dx, alpha * dx / c2, c1, c2, eta0, steps, riemann_edges(), name="batched")
-        cfg["left"] = (left[0], left[1], 0.0, left[2])
-        cfg["right"] = (right[0], right[1], 0.0, right[2])
-        cfg["x_disc"] = 0.5
-        cfg["fast"] = fast
-        out.append(cfg)
-    return out, rejected
+        else:
+            raise RuntimeError("slot %d: no accepted draw in %d attempts" % (p, max_attempts))
+    return out, {"vacuum_redraws": vac, "unstable_redraws": unstable, "screened": rejected is not None}
