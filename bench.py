@@ -43,7 +43,7 @@ def kernel_source_hash():
 def measured_traffic(kernel, prec):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
     taken from the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_step_roofline_grid.json")
+    path = os.path.join(ROOT, "profiles", "traffic_step_roofline_grid.txt")
     try:
         with open(path) as fh:
             d = json.load(fh)
@@ -105,6 +105,28 @@ def time_step(prec, steps, warmup, dev):
     del fa, fb, out
     torch.cuda.empty_cache()
     return res
+
+
+def copy_bandwidth(dev, nbytes=9 * 2048 * 8192 * 8, reps=20):
+    """Device-to-device copy of an array the size of the FP64 distribution array
+    (torch's copy kernel): the bandwidth a plain streaming kernel reaches here."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * nbytes, "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
 def bench_batched(dev, steps=2000, nprob=256):
@@ -255,6 +277,10 @@ def main():
         res[prec] = time_step(prec, args.steps, args.warmup, dev)
         log(prec, json.dumps(res[prec]))
     head = "f64" if "f64" in res else "f32"
+    log("timing a device copy of the same size")
+    copy = copy_bandwidth(dev)
+    for r_ in res.values():
+        r_["roofline"]["frac_of_device_copy"] = r_["roofline"]["achieved"] / copy["gbs"]
     extras = {}
     if not args.no_extras:
         log("timing batched problems")
@@ -280,6 +306,7 @@ def main():
                                % tuple(r["grid"]), "storage": head},
         "roofline": r["roofline"],
         "cpu_baseline": cpu,
+        "device_copy": copy,
     }
     if "f32" in res and head != "f32":
         line["fp32_storage"] = {"value": res["f32"]["mlups"], "unit": "MLUPS", "ms_per_step": res["f32"]["ms_per_step"],

@@ -105,9 +105,12 @@ typedef struct {
   lb_edge edge[4];     /* x-, x+, y-, y+ */
 } lb_grid;
 
-/* Launch shape of the step kernels: block_x threads per block (64, 128 or 256,
- * one column each) and `rows` rows marched per block (>= 1). {0,0} = default. */
-typedef struct { int32_t block_x, rows; } lb_tile;
+/* Launch shape of the step kernels. The grid is cut into tiles of block_x
+ * columns (64, 128 or 256: one thread per column) by `rows` rows (>= 1).
+ * blocks = 0 launches one block per tile; blocks > 0 launches that many
+ * persistent blocks (rounded down to a multiple of 8), each looping over tiles.
+ * All zero = default {256, 16, 0}. */
+typedef struct { int32_t block_x, rows, blocks; } lb_tile;
 
 /* Fill grid->lambda with Eq. (SEC-VON-13): c1 dx, c1 dx/10 (i = 1..4), 0 (i = 5..8). */
 lb_status lb_default_lambda(lb_grid* grid);

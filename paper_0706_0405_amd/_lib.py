@@ -6,7 +6,7 @@ import os
 from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_uint32, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbkt.so")
+LIB_PATH = os.environ.get("LBKT_LIB") or os.path.join(HERE, "liblbkt.so")
 
 LB_F64, LB_F32 = 0, 1
 BC = {"periodic": 0, "outflow": 1, "wall": 2, "inflow": 3, "shock": 4}
@@ -29,7 +29,7 @@ class LbGrid(ctypes.Structure):
 
 
 class LbTile(ctypes.Structure):
-    _fields_ = [("block_x", c_int32), ("rows", c_int32)]
+    _fields_ = [("block_x", c_int32), ("rows", c_int32), ("blocks", c_int32)]
 
 
 class LbError(RuntimeError):

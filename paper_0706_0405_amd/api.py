@@ -125,9 +125,11 @@ def init(grid: Grid, rho, ux, uy, p, prec="f64", out=None):
 
 
 def _tile(tile):
+    """(block_x, rows[, blocks]) -> lb_tile; None = the library default."""
     if tile is None:
         return None
-    return ctypes.byref(LbTile(int(tile[0]), int(tile[1])))
+    blocks = int(tile[2]) if len(tile) > 2 else 0
+    return ctypes.byref(LbTile(int(tile[0]), int(tile[1]), blocks))
 
 
 def step(grid: Grid, f_in, f_out, n=0, prec="f64", tile=None):
@@ -206,7 +208,7 @@ def autotune(grid: Grid, f_a, f_b, prec="f64", reps=10):
     ms = ctypes.c_float()
     check(lib().lb_autotune(ctypes.byref(grid.c()), pr, _ptr(f_a), _ptr(f_b), int(reps), ctypes.byref(best),
                             ctypes.byref(ms), _stream(f_a.device)))
-    return (best.block_x, best.rows), ms.value
+    return (best.block_x, best.rows, best.blocks), ms.value
 
 
 def interior(grid: Grid, f):
@@ -243,7 +245,7 @@ class Batch:
         return buf[o:o + 9 * g.ny * self.pitches[p]].view(9, g.ny, self.pitches[p])
 
     def set_tile(self, block_x):
-        check(lib().lb_batch_set_tile(self.h, ctypes.byref(LbTile(int(block_x), 0))))
+        check(lib().lb_batch_set_tile(self.h, ctypes.byref(LbTile(int(block_x), 0, 0))))
 
     def step(self, f_a, f_b, nsteps):
         """nsteps steps of every problem in one graph launch; returns the result buffer."""

@@ -167,6 +167,18 @@ __host__ __device__ __forceinline__ double wcoef(const KTConsts& K, int i, int k
   return up ? K.upd : K.dnd;
 }
 
+// Linear part and relaxation of plane i at one site (the fixed operation order
+// every kernel uses).
+__host__ __device__ __forceinline__ double plane_update(const KTConsts& K, int i, double fe, double c, double xp,
+                                                        double xm, double yp, double ym) {
+  double acc = K.inv_tau * fe;
+  acc = fma(wcoef(K, i, 4), ym, acc);
+  acc = fma(wcoef(K, i, 3), yp, acc);
+  acc = fma(wcoef(K, i, 2), xm, acc);
+  acc = fma(wcoef(K, i, 1), xp, acc);
+  return fma(wcoef(K, i, 0), c, acc);
+}
+
 // One site of the step: centre values c, neighbours at x+dx, x-dx, y+dy, y-dy.
 __host__ __device__ __forceinline__ void site_update(const KTConsts& K, const double c[9], const double xp[9],
                                                      const double xm[9], const double yp[9], const double ym[9],
@@ -175,14 +187,7 @@ __host__ __device__ __forceinline__ void site_update(const KTConsts& K, const do
   double fe[9];
   feq9(K, P.rho, P.ux, P.uy, P.T, P.usq, fe);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    double acc = K.inv_tau * fe[i];
-    acc = fma(wcoef(K, i, 4), ym[i], acc);
-    acc = fma(wcoef(K, i, 3), yp[i], acc);
-    acc = fma(wcoef(K, i, 2), xm[i], acc);
-    acc = fma(wcoef(K, i, 1), xp[i], acc);
-    out[i] = fma(wcoef(K, i, 0), c[i], acc);
-  }
+  for (int i = 0; i < 9; ++i) out[i] = plane_update(K, i, fe[i], c[i], xp[i], xm[i], yp[i], ym[i]);
 }
 
 // Mirror maps of a reflecting wall: x-normal swaps 1<->3, 5<->6, 7<->8;

@@ -219,6 +219,24 @@ static int shock_cells(const lb_grid* g, int e, int64_t step) {
 // (they read 0 / are dropped by the hardware). Arrays must be below 4 GiB.
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 #define LB_RSRC_WORD3 0x00020000
+// cache policy of the distribution stores: non-temporal (the next step reads
+// them only after the whole array has streamed through the caches)
+#ifndef LB_STORE_AUX
+#define LB_STORE_AUX 2
+#endif
+// cache policy of the streamed row loads of the step kernels (0: default)
+#ifndef LB_LOAD_AUX
+#define LB_LOAD_AUX 0
+#endif
+// minimum waves per SIMD requested for the step kernels (0: compiler's choice)
+#ifndef LB_STEP_WAVES
+#define LB_STEP_WAVES 0
+#endif
+#if LB_STEP_WAVES > 0
+#define LB_STEP_ATTR __attribute__((amdgpu_waves_per_eu(LB_STEP_WAVES)))
+#else
+#define LB_STEP_ATTR
+#endif
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, LB_RSRC_WORD3);
@@ -230,7 +248,7 @@ template <> struct Mem<double> {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vb, (int)sb, 0));
   }
   static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vb, (int)sb, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vb, (int)sb, LB_STORE_AUX);
   }
 };
 template <> struct Mem<float> {
@@ -238,7 +256,8 @@ template <> struct Mem<float> {
     return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vb, (int)sb, 0));
   }
   static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb, double v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)v), r, (int)vb, (int)sb, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)v), r, (int)vb, (int)sb,
+                                          LB_STORE_AUX);
   }
 };
 
@@ -305,11 +324,11 @@ template <typename S>
 __device__ __forceinline__ S ld_raw(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb);
 template <>
 __device__ __forceinline__ double ld_raw<double>(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vb, (int)sb, 0));
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vb, (int)sb, LB_LOAD_AUX));
 }
 template <>
 __device__ __forceinline__ float ld_raw<float>(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vb, (int)sb, 0));
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vb, (int)sb, LB_LOAD_AUX));
 }
 
 template <typename S>
@@ -391,6 +410,8 @@ __device__ __forceinline__ void ghost_x(const KTConsts& K, const View<S>& f, int
 
 // Site update of row y for one lane: prev/cur/nxt are the rows y-1, y, y+1 at
 // the lane's column, hc the halo values of row y (lanes 0 and 63).
+// Site update of row y for one lane: prev/cur/nxt are the rows y-1, y, y+1 at
+// the lane's column, hc the halo values of row y (lanes 0 and 63).
 template <bool XEDGE, typename S>
 __device__ __forceinline__ void row_update(const KTConsts& K, const View<S>& fi, const View<S>& fo, const Lane& L,
                                            int y, const double prev[9], const double cur[9], const double nxt[9],
@@ -432,12 +453,14 @@ __device__ __forceinline__ void march(const KTConsts& K, const View<S>& fi, cons
   for (int i = 0; i < 9; ++i) HC[i] = (S)0;
   if (L.halo) load_raw9(fi, (uint32_t)y0 * fi.rowB + L.vbh, HC);
   if (y0 + 1 < ny) load_raw9(fi, (uint32_t)(y0 + 1) * fi.rowB + L.vbx, N);
+  // rows beyond y1 are needed only as the upper neighbour of row y1-1
+  const int ylast = min(y1, ny - 1);
   for (int y = y0; y < y1; ++y) {
     // issue the fetches of row y+2 and of the halo of row y+1
-    if (y + 2 < ny) load_raw9(fi, (uint32_t)(y + 2) * fi.rowB + L.vbx, F);
+    if (y + 2 <= ylast) load_raw9(fi, (uint32_t)(y + 2) * fi.rowB + L.vbx, F);
 #pragma unroll
     for (int i = 0; i < 9; ++i) HN[i] = (S)0;
-    if (L.halo && y + 1 < ny) load_raw9(fi, (uint32_t)(y + 1) * fi.rowB + L.vbh, HN);
+    if (L.halo && y + 1 < y1) load_raw9(fi, (uint32_t)(y + 1) * fi.rowB + L.vbh, HN);
     if (y + 1 < ny) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) nd[i] = (double)N[i];
@@ -469,23 +492,28 @@ __device__ __forceinline__ void tile_of_block(int id, int nstrips, int nblocks, 
   *chunk = lin / nstrips;
 }
 
+// Blocks loop over tile ids id = blockIdx.x, blockIdx.x + gridDim.x, ... (one
+// tile per block when gridDim.x equals the tile count). gridDim.x is a multiple
+// of 8 whenever xcd_map is set, so every tile of a block stays in its XCD's band.
 template <typename S>
-__global__ __launch_bounds__(256) void k_step(KTConsts K, const S* __restrict__ fin, S* __restrict__ fout,
-                                              int rows, int nstrips, int nblocks, int xcd_map, int ish_lo,
-                                              int ish_hi) {
-  int strip, chunk;
-  tile_of_block(blockIdx.x, nstrips, nblocks, xcd_map, &strip, &chunk);
-  const int lane = threadIdx.x & 63;
-  const int xw0 = strip * blockDim.x + (threadIdx.x & ~63);
-  if (xw0 >= K.nx) return;   // whole wavefront beyond the grid
-  const int y0 = chunk * rows;
-  const int y1 = min(y0 + rows, K.ny);
+__global__ __launch_bounds__(256) LB_STEP_ATTR void k_step(KTConsts K, const S* __restrict__ fin,
+                                                           S* __restrict__ fout, int rows, int nstrips, int ntiles,
+                                                           int xcd_map, int ish_lo, int ish_hi) {
   const View<S> fi = make_view<S>(K, fin), fo = make_view<S>(K, fout);
-  const Lane L = make_lane<S>(K, xw0, lane);
-  if (xw0 == 0 || xw0 + 64 >= K.nx)
-    march<true>(K, fi, fo, L, y0, y1, ish_lo, ish_hi);
-  else
-    march<false>(K, fi, fo, L, y0, y1, ish_lo, ish_hi);
+  const int lane = threadIdx.x & 63;
+  for (int id = blockIdx.x; id < ntiles; id += gridDim.x) {
+    int strip, chunk;
+    tile_of_block(id, nstrips, ntiles, xcd_map, &strip, &chunk);
+    const int xw0 = strip * blockDim.x + (threadIdx.x & ~63);
+    if (xw0 >= K.nx) continue;   // whole wavefront beyond the grid
+    const int y0 = chunk * rows;
+    const int y1 = min(y0 + rows, K.ny);
+    const Lane L = make_lane<S>(K, xw0, lane);
+    if (xw0 == 0 || xw0 + 64 >= K.nx)
+      march<true>(K, fi, fo, L, y0, y1, ish_lo, ish_hi);
+    else
+      march<false>(K, fi, fo, L, y0, y1, ish_lo, ish_hi);
+  }
 }
 
 template <typename S>
@@ -746,34 +774,44 @@ static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   return pa < pb + nb && pb < pa + na;
 }
 
-static lb_status resolve_tile(const lb_tile* tile, int ny, int* bx, int* rows) {
-  int b = 256, r = 32;
-  if (tile && (tile->block_x || tile->rows)) {
+struct Tile {
+  int bx, rows, blocks;
+};
+
+static lb_status resolve_tile(const lb_tile* tile, int ny, Tile* t) {
+  int b = 256, r = 16, nb = 0;
+  if (tile && (tile->block_x || tile->rows || tile->blocks)) {
     b = tile->block_x;
     r = tile->rows;
+    nb = tile->blocks;
   }
   if (b != 64 && b != 128 && b != 256) return fail(LB_EINVAL, "tile block_x must be 64, 128 or 256");
   if (r < 1) return fail(LB_EINVAL, "tile rows must be >= 1");
-  *bx = b;
-  *rows = std::min(r, ny);
+  if (nb < 0) return fail(LB_EINVAL, "tile blocks must be >= 0");
+  t->bx = b;
+  t->rows = std::min(r, ny);
+  t->blocks = nb;
   return LB_OK;
 }
 
 static lb_status launch_step(const lb_grid* g, const KTConsts& K, lb_prec prec, const void* fin, void* fout,
-                             int64_t step, int bx, int rows, hipStream_t st) {
+                             int64_t step, const Tile& t, hipStream_t st) {
+  const int bx = t.bx, rows = t.rows;
   const int nstrips = (g->nx + bx - 1) / bx;
   const int nchunks = (g->ny + rows - 1) / rows;
-  const int64_t nblocks64 = (int64_t)nstrips * nchunks;
-  if (nblocks64 > 0x7fffffff) return fail(LB_EINVAL, "grid too large for one launch");
-  const int nblocks = (int)nblocks64;
-  const int xcd_map = (nblocks % 8 == 0 && nchunks % 8 == 0) ? 1 : 0;
+  const int64_t ntiles64 = (int64_t)nstrips * nchunks;
+  if (ntiles64 > 0x7fffffff) return fail(LB_EINVAL, "grid too large for one launch");
+  const int ntiles = (int)ntiles64;
+  const int xcd_map = (ntiles % 8 == 0) ? 1 : 0;
+  int nblocks = ntiles;
+  if (t.blocks > 0 && t.blocks < ntiles) nblocks = xcd_map ? std::max(8, t.blocks & ~7) : t.blocks;
   const int ish_lo = shock_cells(g, 2, step), ish_hi = shock_cells(g, 3, step);
   if (prec == LB_F64)
     hipLaunchKernelGGL(k_step<double>, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fin, (double*)fout,
-                       rows, nstrips, nblocks, xcd_map, ish_lo, ish_hi);
+                       rows, nstrips, ntiles, xcd_map, ish_lo, ish_hi);
   else
     hipLaunchKernelGGL(k_step<float>, dim3(nblocks), dim3(bx), 0, st, K, (const float*)fin, (float*)fout,
-                       rows, nstrips, nblocks, xcd_map, ish_lo, ish_hi);
+                       rows, nstrips, ntiles, xcd_map, ish_lo, ish_hi);
   HIP_CHECK(hipGetLastError());
   return LB_OK;
 }
@@ -810,11 +848,11 @@ extern "C" lb_status lb_step_tiled(const lb_grid* g, lb_prec prec, const void* f
     return s;
   const size_t bytes = (size_t)lb_array_elems(g) * elem_size(prec);
   if (overlap(fin, bytes, fout, bytes)) return fail(LB_EALIAS, "f_in and f_out overlap");
-  int bx, rows;
-  if ((s = resolve_tile(tile, g->ny, &bx, &rows))) return s;
+  Tile t;
+  if ((s = resolve_tile(tile, g->ny, &t))) return s;
   KTConsts K;
   build_consts(g, &K);
-  return launch_step(g, K, prec, fin, fout, step, bx, rows, (hipStream_t)stream);
+  return launch_step(g, K, prec, fin, fout, step, t, (hipStream_t)stream);
 }
 
 extern "C" lb_status lb_step(const lb_grid* g, lb_prec prec, const void* fin, void* fout, int64_t step,
@@ -850,8 +888,8 @@ extern "C" lb_status lb_run(const lb_grid* g, lb_prec prec, void* fa, void* fb, 
   if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
   const size_t bytes = (size_t)lb_array_elems(g) * elem_size(prec);
   if (overlap(fa, bytes, fb, bytes)) return fail(LB_EALIAS, "f_a and f_b overlap");
-  int bx, rows;
-  if ((s = resolve_tile(tile, g->ny, &bx, &rows))) return s;
+  Tile t;
+  if ((s = resolve_tile(tile, g->ny, &t))) return s;
   KTConsts K;
   build_consts(g, &K);
   hipStream_t st = (hipStream_t)stream;
@@ -859,11 +897,11 @@ extern "C" lb_status lb_run(const lb_grid* g, lb_prec prec, void* fa, void* fb, 
     for (int n = 0; n < nsteps; ++n) {
       const void* in = (n % 2 == 0) ? fa : fb;
       void* out = (n % 2 == 0) ? fb : fa;
-      if ((s = launch_step(g, K, prec, in, out, step0 + n, bx, rows, st))) return s;
+      if ((s = launch_step(g, K, prec, in, out, step0 + n, t, st))) return s;
     }
     return LB_OK;
   }
-  const std::string key = run_key(g, prec, fa, fb, step0, nsteps, bx, rows, stream);
+  const std::string key = run_key(g, prec, fa, fb, step0, nsteps, t.bx, t.rows * 1000003 + t.blocks, stream);
   std::lock_guard<std::mutex> lock(g_graph_mu);
   for (auto& e : g_graphs)
     if (e.key == key) {
@@ -875,7 +913,7 @@ extern "C" lb_status lb_run(const lb_grid* g, lb_prec prec, void* fa, void* fb, 
   for (int n = 0; n < nsteps && ls == LB_OK; ++n) {
     const void* in = (n % 2 == 0) ? fa : fb;
     void* out = (n % 2 == 0) ? fb : fa;
-    ls = launch_step(g, K, prec, in, out, step0 + n, bx, rows, st);
+    ls = launch_step(g, K, prec, in, out, step0 + n, t, st);
   }
   hipGraph_t graph = nullptr;
   hipError_t ce = hipStreamEndCapture(st, &graph);
@@ -1196,32 +1234,36 @@ extern "C" lb_status lb_autotune(const lb_grid* g, lb_prec prec, void* fa, void*
   HIP_CHECK(hipEventCreate(&e1));
   const int bxs[3] = {64, 128, 256};
   const int rws[6] = {4, 8, 16, 32, 64, 128};
+  const int nbs[3] = {0, 1024, 2048};
   float bestv = 1e30f;
-  lb_tile bt = {256, 32};
+  lb_tile bt = {256, 16, 0};
   KTConsts K;
   build_consts(g, &K);
   for (int bi = 0; bi < 3; ++bi)
-    for (int ri = 0; ri < 6; ++ri) {
-      const int bx = bxs[bi], rows = std::min(rws[ri], g->ny);
-      if (ri > 0 && rows == std::min(rws[ri - 1], g->ny)) continue;
-      // warm-up launch, then reps timed launches
-      if ((s = launch_step(g, K, prec, fa, fb, 0, bx, rows, st))) goto done;
-      if (hipEventRecord(e0, st) != hipSuccess) { s = fail(LB_EHIP, "event record"); goto done; }
-      for (int n = 0; n < reps; ++n)
-        if ((s = launch_step(g, K, prec, (n % 2 == 0) ? fb : fa, (n % 2 == 0) ? fa : fb, 0, bx, rows, st))) goto done;
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-        s = fail(LB_EHIP, "event sync");
-        goto done;
+    for (int ri = 0; ri < 6; ++ri)
+      for (int ni = 0; ni < 3; ++ni) {
+        const int bx = bxs[bi], rows = std::min(rws[ri], g->ny);
+        if (ri > 0 && rows == std::min(rws[ri - 1], g->ny)) continue;
+        const Tile t = {bx, rows, nbs[ni]};
+        // warm-up launch, then reps timed launches
+        if ((s = launch_step(g, K, prec, fa, fb, 0, t, st))) goto done;
+        if (hipEventRecord(e0, st) != hipSuccess) { s = fail(LB_EHIP, "event record"); goto done; }
+        for (int n = 0; n < reps; ++n)
+          if ((s = launch_step(g, K, prec, (n % 2 == 0) ? fb : fa, (n % 2 == 0) ? fa : fb, 0, t, st))) goto done;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          s = fail(LB_EHIP, "event sync");
+          goto done;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < bestv) {
+          bestv = ms;
+          bt.block_x = bx;
+          bt.rows = rows;
+          bt.blocks = nbs[ni];
+        }
       }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      ms /= reps;
-      if (ms < bestv) {
-        bestv = ms;
-        bt.block_x = bx;
-        bt.rows = rows;
-      }
-    }
 done:
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -23,6 +23,12 @@ def _fields(cfg):
     return [torch.tensor(np.ascontiguousarray(a), dtype=F64, device=DEV) for a in P.init_fields(cfg)]
 
 
+def _bits(t):
+    """Bit pattern of a float tensor (NaN payloads included) for exact comparison."""
+    t = t.contiguous()
+    return t.view(torch.int32 if t.dtype == torch.float32 else torch.int64)
+
+
 def _make(cfgs, prec="f32"):
     lb = _lb()
     grids = [lb.Grid.from_workload(c) for c in cfgs]
@@ -61,7 +67,7 @@ def test_batched_equals_single_runs_bitwise(block_x):
         f1 = lb.init(g, *_fields(c), prec="f32")
         f2 = lb.empty(g, "f32", DEV)
         r = lb.run(g, f1, f2, 200, prec="f32")
-        assert torch.equal(r[:, :, :g.nx], B.view(out, k)[:, :, :g.nx]), k
+        assert torch.equal(_bits(r[:, :, :g.nx]), _bits(B.view(out, k)[:, :, :g.nx])), k
 
 
 def test_graph_replays_continue_the_run():
@@ -76,7 +82,7 @@ def test_graph_replays_continue_the_run():
         f1 = B.view(ref_a, k).clone()
         f2 = torch.empty_like(f1)
         r = lb.run(g, f1, f2, 200, prec="f32")
-        assert torch.equal(r[:, :, :g.nx], B.view(out, k)[:, :, :g.nx]), k
+        assert torch.equal(_bits(r[:, :, :g.nx]), _bits(B.view(out, k)[:, :, :g.nx])), k
 
 
 def test_batched_against_oracle_fp32_bound():

@@ -117,7 +117,8 @@ def test_tau_beta_variants(tau, beta):
 
 # ------------------------------------------------------------------ bitwise properties
 
-TILES = [(64, 1), (64, 5), (128, 16), (256, 32), (256, 240), (128, 3)]
+TILES = [(64, 1, 0), (64, 5, 0), (128, 16, 0), (256, 32, 0), (256, 240, 0), (128, 3, 0), (256, 16, 1024),
+         (128, 7, 40), (64, 9, 13), None]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
