@@ -109,7 +109,8 @@ typedef struct {
  * columns (64, 128 or 256: one thread per column) by `rows` rows (>= 1).
  * blocks = 0 launches one block per tile; blocks > 0 launches that many
  * persistent blocks (rounded down to a multiple of 8), each looping over tiles.
- * All zero = default {256, 16, 0}. */
+ * All zero (or a NULL tile) = the default: 256 x 16 tiles, one block per tile,
+ * shrunk on small grids (rows down to 2, then columns) to give at least 1024 tiles. */
 typedef struct { int32_t block_x, rows, blocks; } lb_tile;
 
 /* Fill grid->lambda with Eq. (SEC-VON-13): c1 dx, c1 dx/10 (i = 1..4), 0 (i = 5..8). */
@@ -163,6 +164,20 @@ lb_status lb_invariants(const lb_grid* grid, lb_prec prec, const void* f, double
  * of v, no limiter, so the step is smooth in f where rho != 0). */
 lb_status lb_step_adjoint(const lb_grid* grid, lb_prec prec, const void* f_n, const double* g_np1,
                           double* g_n, int64_t step, void* stream);
+
+/* nsteps steps from f0, keeping every state: out[j] (a host array of nsteps
+ * device pointers, each a distribution array of the storage type) receives the
+ * state after step step0 + j. Used to recompute a checkpointed segment. */
+lb_status lb_run_record(const lb_grid* grid, lb_prec prec, const void* f0, void* const* out, int64_t step0,
+                        int32_t nsteps, void* stream);
+
+/* Reverse sweep over nsteps steps: f[j] (host array of nsteps device pointers) is
+ * the state at time index step0 + j; g holds g^{step0+nsteps} on entry. Applies
+ * lb_step_adjoint for j = nsteps-1 .. 0, alternating between g and work (both
+ * float64 distribution arrays, not overlapping); g^{step0} ends in g when nsteps
+ * is even, else in work. */
+lb_status lb_adjoint_run(const lb_grid* grid, lb_prec prec, const void* const* f, double* g, double* work,
+                         int64_t step0, int32_t nsteps, void* stream);
 
 /* Adjoint of lb_init with respect to rho at fixed u and p:
  * g_rho[x] = sum_i g_f0_i(x) d f_i^eq(rho, u, p/rho) / d rho. */

@@ -54,6 +54,10 @@ _SIGS = {
                              c_void_p, c_void_p]),
     "lb_invariants": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, c_void_p, c_void_p]),
     "lb_step_adjoint": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
+    "lb_run_record": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, POINTER(c_void_p), c_int64, c_int32,
+                                c_void_p]),
+    "lb_adjoint_run": (c_int32, [POINTER(LbGrid), c_int32, POINTER(c_void_p), c_void_p, c_void_p, c_int64,
+                                 c_int32, c_void_p]),
     "lb_init_adjoint": (c_int32, [POINTER(LbGrid), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p]),
     "lb_batch_create": (c_int32, [c_int32, POINTER(LbGrid), c_int32, POINTER(c_void_p)]),

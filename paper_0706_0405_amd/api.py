@@ -188,6 +188,31 @@ def step_adjoint(grid: Grid, f_n, g_np1, g_n=None, n=0, prec="f64"):
     return g_n
 
 
+def run_record(grid: Grid, f0, outs, n0=0, prec="f64"):
+    """outs[j] = state after step n0 + j from f0 (lb_run_record)."""
+    pr = _prec(prec)
+    _check_f(grid, pr, f0, "f0")
+    for o in outs:
+        _check_f(grid, pr, o, "out")
+    arr = (ctypes.c_void_p * max(1, len(outs)))(*[o.data_ptr() for o in outs])
+    check(lib().lb_run_record(ctypes.byref(grid.c()), pr, _ptr(f0), arr, int(n0), len(outs), _stream(f0.device)))
+    return outs
+
+
+def adjoint_run(grid: Grid, states, g, work, n0=0, prec="f64"):
+    """Reverse sweep over states (f at n0 .. n0+len-1) starting from g = dL/df^(n0+len);
+    returns the tensor (g or work) that holds dL/df^(n0) (lb_adjoint_run)."""
+    pr = _prec(prec)
+    for t in states:
+        _check_f(grid, pr, t, "state")
+    _check_f(grid, LB_F64, g, "g")
+    _check_f(grid, LB_F64, work, "work")
+    arr = (ctypes.c_void_p * max(1, len(states)))(*[t.data_ptr() for t in states])
+    check(lib().lb_adjoint_run(ctypes.byref(grid.c()), pr, arr, _ptr(g), _ptr(work), int(n0), len(states),
+                               _stream(g.device)))
+    return g if len(states) % 2 == 0 else work
+
+
 def init_adjoint(grid: Grid, rho, ux, uy, p, g_f0):
     """dL/drho0 from dL/df0 at fixed u and p (lb_init_adjoint)."""
     for t, n in ((rho, "rho"), (ux, "ux"), (uy, "uy"), (p, "p")):

@@ -658,6 +658,100 @@ __device__ __forceinline__ void adj_edge(const KTConsts& K, const double gc[9], 
   }
 }
 
+// One row of the adjoint march: g_n at row y from g_{n+1} rows y-1 (gd), y (gc),
+// y+1 (gu) (zero where a non-periodic edge has no such row), the halo values hc
+// of row y and f_n at the site. Accumulation order: collision adjoint, then
+// the y+1, y-1, x+1, x-1 and centre terms, then the own-ghost corrections.
+template <bool XEDGE, typename S>
+__device__ __forceinline__ void adj_row(const KTConsts& K, const View<double>& gi, const View<double>& go,
+                                        const Lane& L, uint32_t vbg, int y, const double gd[9], const double gc[9],
+                                        const double gu[9], const double hc[9], const S fr[9], bool perx,
+                                        bool pery) {
+  double fc[9], acc[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fc[i] = (double)fr[i];
+  const Prim P = moments9(K, fc);
+  collision_adjoint(K, P, gc, acc);
+  const int x = L.x, nx = K.nx;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    double gr = shl1(hc[i], gc[i]);   // g_{n+1}(x+1): site x is its x-dx neighbour
+    double gl = shr1(hc[i], gc[i]);   // g_{n+1}(x-1): site x is its x+dx neighbour
+    if (XEDGE) {
+      if (x == 0 && !perx) gl = 0.0;
+      if (x == nx - 1) gr = perx ? Mem<double>::ld(gi.r, (uint32_t)y * gi.rowB, (uint32_t)i * gi.planeB) : 0.0;
+    }
+    double a = acc[i];
+    a = fma(wcoef(K, i, 4), gu[i], a);
+    a = fma(wcoef(K, i, 3), gd[i], a);
+    a = fma(wcoef(K, i, 2), gr, a);
+    a = fma(wcoef(K, i, 1), gl, a);
+    acc[i] = fma(wcoef(K, i, 0), gc[i], a);
+  }
+  if (XEDGE) {
+    if (x == 0 && !perx) adj_edge<0>(K, gc, y, acc);
+    if (x == nx - 1 && !perx) adj_edge<1>(K, gc, y, acc);
+  }
+  if (y == 0 && !pery) adj_edge<2>(K, gc, x, acc);
+  if (y == K.ny - 1 && !pery) adj_edge<3>(K, gc, x, acc);
+  if (x < nx) go.store9((uint32_t)y * go.rowB + vbg, acc);
+}
+
+// Adjoint march over a 64-column wavefront strip, the same structure as the
+// forward march: g_{n+1} rows y-1, y, y+1 in registers, row y+2 and the f_n row
+// y+1 fetched one iteration ahead, x-neighbours through DPP shifts with the two
+// halo columns read by lanes 0 and 63.
+template <bool XEDGE, typename S>
+__device__ __forceinline__ void adj_march(const KTConsts& K, const View<S>& ff, const View<double>& gi,
+                                          const View<double>& go, int xw0, int lane, int y0, int y1) {
+  const int ny = K.ny;
+  const bool perx = (K.kind[0] == BC_PERIODIC), pery = (K.kind[2] == BC_PERIODIC);
+  const Lane L = make_lane<double>(K, xw0, lane);
+  const uint32_t vbf = (uint32_t)L.x * sizeof(S);
+  double pd[9], cd[9], nd[9], N[9], F[9], HC[9], HN[9];
+  S FC[9], FN[9];
+  if (y0 > 0)
+    gi.load9((uint32_t)(y0 - 1) * gi.rowB + L.vbx, pd);
+  else if (pery)
+    gi.load9((uint32_t)(ny - 1) * gi.rowB + L.vbx, pd);
+  else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) pd[i] = 0.0;
+  }
+  gi.load9((uint32_t)y0 * gi.rowB + L.vbx, cd);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) HC[i] = 0.0;
+  if (L.halo) load_raw9(gi, (uint32_t)y0 * gi.rowB + L.vbh, HC);
+  if (y0 + 1 < ny) load_raw9(gi, (uint32_t)(y0 + 1) * gi.rowB + L.vbx, N);
+  load_raw9(ff, (uint32_t)y0 * ff.rowB + vbf, FC);
+  const int ylast = min(y1, ny - 1);
+  for (int y = y0; y < y1; ++y) {
+    if (y + 2 <= ylast) load_raw9(gi, (uint32_t)(y + 2) * gi.rowB + L.vbx, F);
+    if (y + 1 < y1) load_raw9(ff, (uint32_t)(y + 1) * ff.rowB + vbf, FN);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) HN[i] = 0.0;
+    if (L.halo && y + 1 < y1) load_raw9(gi, (uint32_t)(y + 1) * gi.rowB + L.vbh, HN);
+    if (y + 1 < ny) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) nd[i] = N[i];
+    } else if (pery) {
+      gi.load9(L.vbx, nd);   // row 0
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) nd[i] = 0.0;
+    }
+    adj_row<XEDGE>(K, gi, go, L, L.vbx, y, pd, cd, nd, HC, FC, perx, pery);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      pd[i] = cd[i];
+      cd[i] = nd[i];
+      N[i] = F[i];
+      HC[i] = HN[i];
+      FC[i] = FN[i];
+    }
+  }
+}
+
 // g_n = (dS/df)^T g_np1: transposed stencil over g_np1 plus the local collision adjoint.
 template <typename S>
 __global__ __launch_bounds__(256) void k_adjoint(KTConsts K, const S* __restrict__ fn,
@@ -665,50 +759,17 @@ __global__ __launch_bounds__(256) void k_adjoint(KTConsts K, const S* __restrict
                                                  int rows, int nstrips, int nblocks, int xcd_map) {
   int strip, chunk;
   tile_of_block(blockIdx.x, nstrips, nblocks, xcd_map, &strip, &chunk);
-  const int x = strip * blockDim.x + threadIdx.x;
-  if (x >= K.nx) return;
+  const int lane = threadIdx.x & 63;
+  const int xw0 = strip * blockDim.x + (threadIdx.x & ~63);
+  if (xw0 >= K.nx) return;   // whole wavefront beyond the grid
   const int y0 = chunk * rows;
   const int y1 = min(y0 + rows, K.ny);
-  const int nx = K.nx, ny = K.ny;
-  const bool perx = (K.kind[0] == BC_PERIODIC), pery = (K.kind[2] == BC_PERIODIC);
-  const bool hasl = (x > 0) || perx, hasr = (x < nx - 1) || perx;
-  const int xl = (x > 0) ? x - 1 : nx - 1, xr = (x < nx - 1) ? x + 1 : 0;
-  for (int y = y0; y < y1; ++y) {
-    const bool hasd = (y > 0) || pery, hasu = (y < ny - 1) || pery;
-    const int yd = (y > 0) ? y - 1 : ny - 1, yu = (y < ny - 1) ? y + 1 : 0;
-    const double* row = g1 + (int64_t)y * K.pitch;
-    const double* rowd = g1 + (int64_t)yd * K.pitch;
-    const double* rowu = g1 + (int64_t)yu * K.pitch;
-    const S* pf = fn + (int64_t)y * K.pitch + x;
-    double gc[9], fc[9], acc[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      gc[i] = row[i * K.plane + x];
-      fc[i] = ldv(pf + i * K.plane);
-    }
-    const Prim P = moments9(K, fc);
-    collision_adjoint(K, P, gc, acc);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const double gu = hasu ? rowu[i * K.plane + x] : 0.0;
-      const double gd = hasd ? rowd[i * K.plane + x] : 0.0;
-      const double gr = hasr ? row[i * K.plane + xr] : 0.0;
-      const double gl = hasl ? row[i * K.plane + xl] : 0.0;
-      double a = acc[i];
-      a = fma(wcoef(K, i, 4), gu, a);
-      a = fma(wcoef(K, i, 3), gd, a);
-      a = fma(wcoef(K, i, 2), gr, a);
-      a = fma(wcoef(K, i, 1), gl, a);
-      acc[i] = fma(wcoef(K, i, 0), gc[i], a);
-    }
-    if (x == 0 && !perx) adj_edge<0>(K, gc, y, acc);
-    if (x == nx - 1 && !perx) adj_edge<1>(K, gc, y, acc);
-    if (y == 0 && !pery) adj_edge<2>(K, gc, x, acc);
-    if (y == ny - 1 && !pery) adj_edge<3>(K, gc, x, acc);
-    double* po = g0 + (int64_t)y * K.pitch + x;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) po[i * K.plane] = acc[i];
-  }
+  const View<S> ff = make_view<S>(K, fn);
+  const View<double> gi = make_view<double>(K, g1), go = make_view<double>(K, g0);
+  if (xw0 == 0 || xw0 + 64 >= K.nx)
+    adj_march<true>(K, ff, gi, go, xw0, lane, y0, y1);
+  else
+    adj_march<false>(K, ff, gi, go, xw0, lane, y0, y1);
 }
 
 __global__ __launch_bounds__(256) void k_init_adjoint(KTConsts K, const double* __restrict__ rho,
@@ -778,8 +839,21 @@ struct Tile {
   int bx, rows, blocks;
 };
 
-static lb_status resolve_tile(const lb_tile* tile, int ny, Tile* t) {
-  int b = 256, r = 16, nb = 0;
+// Default launch shape: 256 x 16 tiles on large grids; on smaller grids the
+// tile shrinks (rows first, down to 2, then columns) until there are at least
+// 1024 tiles, four per compute unit.
+static void default_tile(int nx, int ny, int* bx, int* rows) {
+  auto ntiles = [&](int b, int r) { return (int64_t)((nx + b - 1) / b) * ((ny + r - 1) / r); };
+  int b = 256, r = 16;
+  while (ntiles(b, r) < 1024 && r > 2) r /= 2;
+  while (ntiles(b, r) < 1024 && b > 64) b /= 2;
+  *bx = b;
+  *rows = r;
+}
+
+static lb_status resolve_tile(const lb_tile* tile, int nx, int ny, Tile* t) {
+  int b, r, nb = 0;
+  default_tile(nx, ny, &b, &r);
   if (tile && (tile->block_x || tile->rows || tile->blocks)) {
     b = tile->block_x;
     r = tile->rows;
@@ -849,7 +923,7 @@ extern "C" lb_status lb_step_tiled(const lb_grid* g, lb_prec prec, const void* f
   const size_t bytes = (size_t)lb_array_elems(g) * elem_size(prec);
   if (overlap(fin, bytes, fout, bytes)) return fail(LB_EALIAS, "f_in and f_out overlap");
   Tile t;
-  if ((s = resolve_tile(tile, g->ny, &t))) return s;
+  if ((s = resolve_tile(tile, g->nx, g->ny, &t))) return s;
   KTConsts K;
   build_consts(g, &K);
   return launch_step(g, K, prec, fin, fout, step, t, (hipStream_t)stream);
@@ -889,7 +963,7 @@ extern "C" lb_status lb_run(const lb_grid* g, lb_prec prec, void* fa, void* fb, 
   const size_t bytes = (size_t)lb_array_elems(g) * elem_size(prec);
   if (overlap(fa, bytes, fb, bytes)) return fail(LB_EALIAS, "f_a and f_b overlap");
   Tile t;
-  if ((s = resolve_tile(tile, g->ny, &t))) return s;
+  if ((s = resolve_tile(tile, g->nx, g->ny, &t))) return s;
   KTConsts K;
   build_consts(g, &K);
   hipStream_t st = (hipStream_t)stream;
@@ -1002,6 +1076,25 @@ extern "C" lb_status lb_invariants(const lb_grid* g, lb_prec prec, const void* f
   return LB_OK;
 }
 
+static lb_status launch_adjoint(const lb_grid* g, const KTConsts& K, lb_prec prec, const void* fn, const double* g1,
+                                double* g0, hipStream_t st) {
+  int bx, rows;
+  default_tile(g->nx, g->ny, &bx, &rows);
+  rows = std::min(rows, g->ny);
+  const int nstrips = (g->nx + bx - 1) / bx;
+  const int nchunks = (g->ny + rows - 1) / rows;
+  const int nblocks = nstrips * nchunks;
+  const int xcd_map = (nblocks % 8 == 0) ? 1 : 0;
+  if (prec == LB_F64)
+    hipLaunchKernelGGL(k_adjoint<double>, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fn, g1, g0, rows,
+                       nstrips, nblocks, xcd_map);
+  else
+    hipLaunchKernelGGL(k_adjoint<float>, dim3(nblocks), dim3(bx), 0, st, K, (const float*)fn, g1, g0, rows,
+                       nstrips, nblocks, xcd_map);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
 extern "C" lb_status lb_step_adjoint(const lb_grid* g, lb_prec prec, const void* fn, const double* g1, double* g0,
                                      int64_t step, void* stream) {
   (void)step;  // the step's dependence on t (SHOCK ghosts) does not involve f
@@ -1013,19 +1106,50 @@ extern "C" lb_status lb_step_adjoint(const lb_grid* g, lb_prec prec, const void*
   if (overlap(g1, gbytes, g0, gbytes)) return fail(LB_EALIAS, "g_np1 and g_n overlap");
   KTConsts K;
   build_consts(g, &K);
-  const int bx = 256, rows = std::min(32, g->ny);
-  const int nstrips = (g->nx + bx - 1) / bx;
-  const int nchunks = (g->ny + rows - 1) / rows;
-  const int nblocks = nstrips * nchunks;
-  const int xcd_map = (nblocks % 8 == 0 && nchunks % 8 == 0) ? 1 : 0;
+  return launch_adjoint(g, K, prec, fn, g1, g0, (hipStream_t)stream);
+}
+
+extern "C" lb_status lb_adjoint_run(const lb_grid* g, lb_prec prec, const void* const* f, double* gbuf,
+                                    double* work, int64_t step0, int32_t nsteps, void* stream) {
+  (void)step0;
+  lb_status s;
+  if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(gbuf, "g")) || (s = check_ptr(work, "work")))
+    return s;
+  if (nsteps < 0 || (nsteps > 0 && !f)) return fail(LB_EINVAL, "need nsteps >= 0 states");
+  const size_t gbytes = (size_t)lb_array_elems(g) * 8;
+  if (overlap(gbuf, gbytes, work, gbytes)) return fail(LB_EALIAS, "g and work overlap");
+  for (int j = 0; j < nsteps; ++j)
+    if ((s = check_ptr(f[j], "f[j]"))) return s;
+  KTConsts K;
+  build_consts(g, &K);
   hipStream_t st = (hipStream_t)stream;
-  if (prec == LB_F64)
-    hipLaunchKernelGGL(k_adjoint<double>, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fn, g1, g0, rows,
-                       nstrips, nblocks, xcd_map);
-  else
-    hipLaunchKernelGGL(k_adjoint<float>, dim3(nblocks), dim3(bx), 0, st, K, (const float*)fn, g1, g0, rows,
-                       nstrips, nblocks, xcd_map);
-  HIP_CHECK(hipGetLastError());
+  for (int k = 0; k < nsteps; ++k) {
+    const int j = nsteps - 1 - k;
+    const double* in = (k % 2 == 0) ? gbuf : work;
+    double* out = (k % 2 == 0) ? work : gbuf;
+    if ((s = launch_adjoint(g, K, prec, f[j], in, out, st))) return s;
+  }
+  return LB_OK;
+}
+
+extern "C" lb_status lb_run_record(const lb_grid* g, lb_prec prec, const void* f0, void* const* out, int64_t step0,
+                                   int32_t nsteps, void* stream) {
+  lb_status s;
+  if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(f0, "f0"))) return s;
+  if (nsteps < 0 || (nsteps > 0 && !out)) return fail(LB_EINVAL, "need nsteps >= 0 outputs");
+  const size_t bytes = (size_t)lb_array_elems(g) * elem_size(prec);
+  for (int j = 0; j < nsteps; ++j) {
+    if ((s = check_ptr(out[j], "out[j]"))) return s;
+    const void* in = (j == 0) ? f0 : out[j - 1];
+    if (overlap(in, bytes, out[j], bytes)) return fail(LB_EALIAS, "consecutive states overlap");
+  }
+  Tile t;
+  if ((s = resolve_tile(nullptr, g->nx, g->ny, &t))) return s;
+  KTConsts K;
+  build_consts(g, &K);
+  hipStream_t st = (hipStream_t)stream;
+  for (int j = 0; j < nsteps; ++j)
+    if ((s = launch_step(g, K, prec, (j == 0) ? f0 : out[j - 1], out[j], step0 + j, t, st))) return s;
   return LB_OK;
 }
 

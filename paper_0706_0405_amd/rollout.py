@@ -62,19 +62,19 @@ class Rollout:
         gtmp = api.empty(g, "f64", dev)
         gtmp.zero_()
         nseg = len(checkpoints)
-        states = []
+        states = [None] * self.seg
         for s in reversed(range(nseg)):
             start = s * self.seg
             k = min(self.seg, self.n - start)
-            # recompute the segment's states f^start .. f^(start+k-1)
-            states.clear()
-            states.append(checkpoints[s])
+            # recompute the segment's states f^start .. f^(start+k-1), then sweep back over it
             for j in range(1, k):
-                out = api.empty(g, self.prec, dev)
-                api.step(g, states[-1], out, self.n0 + start + j - 1, prec=self.prec)
-                states.append(out)
-            for j in reversed(range(k)):
-                api.step_adjoint(g, states[j], gbuf, gtmp, self.n0 + start + j, prec=self.prec)
+                if states[j] is None:
+                    states[j] = api.empty(g, self.prec, dev)
+            seg_states = [checkpoints[s]] + states[1:k]
+            if k > 1:
+                api.run_record(g, checkpoints[s], seg_states[1:], n0=self.n0 + start, prec=self.prec)
+            res = api.adjoint_run(g, seg_states, gbuf, gtmp, n0=self.n0 + start, prec=self.prec)
+            if res is gtmp:
                 gbuf, gtmp = gtmp, gbuf
         states.clear()
         return api.init_adjoint(g, rho0.detach().to(torch.float64).contiguous(), self.ux0, self.uy0, self.p0, gbuf)
