@@ -19,7 +19,9 @@
  *     0:(0,0) 1:(-c1,0) 2:(0,-c1) 3:(c1,0) 4:(0,c1)
  *     5:(-s,-s) 6:(s,-s) 7:(s,s) 8:(-s,s),   s = c2/sqrt(2)
  * Element (i, y, x) is at  f[i*pitch*ny + y*pitch + x]  (x fastest, pitch >= nx,
- * pitch a multiple of 64 elements, base pointer 256-byte aligned). Site (x, y)
+ * pitch a multiple of 64 elements, base pointer 256-byte aligned; the step
+ * writes unspecified values into the padding columns nx <= x < pitch, and no
+ * entry point reads them as data). Site (x, y)
  * has centre ((x+0.5) dx, (y+0.5) dx). Macroscopic fields (rho, ux, uy, p or T)
  * are dense row-major (ny, nx) float64 arrays.
  *
@@ -109,7 +111,7 @@ typedef struct {
  * columns (64, 128 or 256: one thread per column) by `rows` rows (>= 1).
  * blocks = 0 launches one block per tile; blocks > 0 launches that many
  * persistent blocks (rounded down to a multiple of 8), each looping over tiles.
- * All zero (or a NULL tile) = the default: 256 x 16 tiles, one block per tile,
+ * All zero (or a NULL tile) = the default: 256 x 32 tiles, one block per tile,
  * shrunk on small grids (rows down to 2, then columns) to give at least 1024 tiles. */
 typedef struct { int32_t block_x, rows, blocks; } lb_tile;
 

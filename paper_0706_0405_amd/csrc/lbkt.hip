@@ -408,8 +408,18 @@ __device__ __forceinline__ void ghost_x(const KTConsts& K, const View<S>& f, int
   }
 }
 
-// Site update of row y for one lane: prev/cur/nxt are the rows y-1, y, y+1 at
-// the lane's column, hc the halo values of row y (lanes 0 and 63).
+// Widening of a fetched value at its point of use. For float storage the
+// conversion is written as one asm instruction so that it stays there: as a
+// plain cast the compiler moves it across the loop's phis to just behind the
+// fetch, and waits there for the fetch (and for every store issued before it)
+// instead of a row later. v_cvt_f64_f32 is exact, as the cast is.
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ double widen(float v) {
+  double d;
+  asm volatile("v_cvt_f64_f32 %0, %1" : "=v"(d) : "v"(v));
+  return d;
+}
+
 // Site update of row y for one lane: prev/cur/nxt are the rows y-1, y, y+1 at
 // the lane's column, hc the halo values of row y (lanes 0 and 63).
 template <bool XEDGE, typename S>
@@ -419,7 +429,7 @@ __device__ __forceinline__ void row_update(const KTConsts& K, const View<S>& fi,
   double xm[9], xp[9], out[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const double h = (double)hc[i];
+    const double h = widen(hc[i]);
     xm[i] = shr1(h, cur[i]);
     xp[i] = shl1(h, cur[i]);
   }
@@ -428,53 +438,85 @@ __device__ __forceinline__ void row_update(const KTConsts& K, const View<S>& fi,
     if (L.x == K.nx - 1) ghost_x<1>(K, fi, y, cur, xp);
   }
   site_update(K, cur, xp, xm, nxt, prev, out);
-  if (L.x < K.nx) fo.store9((uint32_t)y * fi.rowB + L.vbx, out);
+  // Lanes past nx store too, into the row's padding columns (x < pitch): no
+  // result reads them, and an unmasked store keeps the compiler's wait counts
+  // from having to cover a path on which the stores were skipped.
+  fo.store9((uint32_t)y * fi.rowB + L.vbx, out);
+}
+
+// One row y < ny-1 of the march: issue the fetches of row y+2 (into F) and of
+// the halo of row y+1 (into HN), widen row y+1 (N, fetched one row earlier),
+// update row y, and shift pd <- cd <- row y+1. Both fetches are issued by every
+// lane on every row, the row clamped into the chunk (a clamped fetch repeats
+// one already made and is served from cache): fetches that are always issued
+// let the compiler count them exactly instead of waiting for them early.
+template <bool XEDGE, typename S>
+__device__ __forceinline__ void march_row(const KTConsts& K, const View<S>& fi, const View<S>& fo, const Lane& L,
+                                          int y, int y1, int ylast, double pd[9], double cd[9], const S N[9],
+                                          const S HC[9], S F[9], S HN[9]) {
+  load_raw9(fi, (uint32_t)min(y + 2, ylast) * fi.rowB + L.vbx, F);
+  load_raw9(fi, (uint32_t)min(y + 1, y1 - 1) * fi.rowB + L.vbh, HN);
+  double nd[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) nd[i] = widen(N[i]);
+  row_update<XEDGE>(K, fi, fo, L, y, pd, cd, nd, HC);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    pd[i] = cd[i];
+    cd[i] = nd[i];
+  }
+  __builtin_amdgcn_sched_barrier(0);   // keep the two unrolled rows apart (register pressure)
+}
+
+// Row y = ny-1, whose upper neighbour is the ghost row of the top edge.
+template <bool XEDGE, typename S>
+__device__ __forceinline__ void top_row(const KTConsts& K, const View<S>& fi, const View<S>& fo, const Lane& L,
+                                        int y, int ish_hi, const double pd[9], const double cd[9], const S HC[9]) {
+  double nd[9];
+  ghost_row<3>(K, fi, L.x, L.vbx, ish_hi, nd);
+  row_update<XEDGE>(K, fi, fo, L, y, pd, cd, nd, HC);
 }
 
 // March a 64-column wavefront strip from row y0 to y1-1. Rows are fetched two
 // rows ahead of the row being updated (so a full iteration of arithmetic hides
 // each fetch), the halo columns one row ahead; x-neighbours come from the
-// adjacent lanes through DPP shifts, and only lanes 0 and 63 read the two
-// halo columns. Every lane runs the whole loop (the DPP shifts need all lanes);
-// lanes beyond nx compute on padding values and store nothing.
+// adjacent lanes through DPP shifts, and only lanes 0 and 63 use the two halo
+// columns. The loop is unrolled by two with two sets of in-flight registers
+// (N0/N1, H0/H1) that swap roles each row, so no value still in flight is ever
+// copied and a row waits only for its own fetches, never for the stores or the
+// fetches issued after them. The top row of the grid (upper neighbour = ghost)
+// is updated after the loop, keeping the ghost's loads and branches out of it.
+// Every lane runs the whole march (the DPP shifts need all lanes); lanes beyond
+// nx compute on padding values and store into the padding.
 template <bool XEDGE, typename S>
 __device__ __forceinline__ void march(const KTConsts& K, const View<S>& fi, const View<S>& fo, const Lane& L,
                                       int y0, int y1, int ish_lo, int ish_hi) {
   const int ny = K.ny;
-  double pd[9], cd[9], nd[9];
-  S N[9], F[9], HC[9], HN[9];
+  double pd[9], cd[9];
+  S N0[9], N1[9], H0[9], H1[9];
   // prologue: row y0-1 (or the bottom ghost), row y0 and its halo, row y0+1
   if (y0 > 0)
     fi.load9((uint32_t)(y0 - 1) * fi.rowB + L.vbx, pd);
   else
     ghost_row<2>(K, fi, L.x, L.vbx, ish_lo, pd);
   fi.load9((uint32_t)y0 * fi.rowB + L.vbx, cd);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) HC[i] = (S)0;
-  if (L.halo) load_raw9(fi, (uint32_t)y0 * fi.rowB + L.vbh, HC);
-  if (y0 + 1 < ny) load_raw9(fi, (uint32_t)(y0 + 1) * fi.rowB + L.vbx, N);
-  // rows beyond y1 are needed only as the upper neighbour of row y1-1
+  load_raw9(fi, (uint32_t)y0 * fi.rowB + L.vbh, H0);
+  load_raw9(fi, (uint32_t)min(y0 + 1, ny - 1) * fi.rowB + L.vbx, N0);
+  // Rows below ylast have a real upper neighbour; ylast is also the last row
+  // fetched (the upper neighbour of row y1-1, unless that is the ghost).
   const int ylast = min(y1, ny - 1);
-  for (int y = y0; y < y1; ++y) {
-    // issue the fetches of row y+2 and of the halo of row y+1
-    if (y + 2 <= ylast) load_raw9(fi, (uint32_t)(y + 2) * fi.rowB + L.vbx, F);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) HN[i] = (S)0;
-    if (L.halo && y + 1 < y1) load_raw9(fi, (uint32_t)(y + 1) * fi.rowB + L.vbh, HN);
-    if (y + 1 < ny) {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) nd[i] = (double)N[i];
-    } else {
-      ghost_row<3>(K, fi, L.x, L.vbx, ish_hi, nd);
-    }
-    row_update<XEDGE>(K, fi, fo, L, y, pd, cd, nd, HC);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      pd[i] = cd[i];
-      cd[i] = nd[i];
-      N[i] = F[i];
-      HC[i] = HN[i];
-    }
+  int y = y0;
+  for (; y + 1 < ylast; y += 2) {
+    march_row<XEDGE>(K, fi, fo, L, y, y1, ylast, pd, cd, N0, H0, N1, H1);
+    march_row<XEDGE>(K, fi, fo, L, y + 1, y1, ylast, pd, cd, N1, H1, N0, H0);
+  }
+  // (the halo set of the next row is picked by branch, not by pointer, so the
+  // arrays stay in registers)
+  if (y < ylast) {
+    march_row<XEDGE>(K, fi, fo, L, y, y1, ylast, pd, cd, N0, H0, N1, H1);
+    if (y + 1 < y1) top_row<XEDGE>(K, fi, fo, L, y + 1, ish_hi, pd, cd, H1);
+  } else if (y < y1) {
+    top_row<XEDGE>(K, fi, fo, L, y, ish_hi, pd, cd, H0);
   }
 }
 
@@ -844,7 +886,7 @@ struct Tile {
 // 1024 tiles, four per compute unit.
 static void default_tile(int nx, int ny, int* bx, int* rows) {
   auto ntiles = [&](int b, int r) { return (int64_t)((nx + b - 1) / b) * ((ny + r - 1) / r); };
-  int b = 256, r = 16;
+  int b = 256, r = 32;
   while (ntiles(b, r) < 1024 && r > 2) r /= 2;
   while (ntiles(b, r) < 1024 && b > 64) b /= 2;
   *bx = b;
