@@ -20,8 +20,8 @@
  *     5:(-s,-s) 6:(s,-s) 7:(s,s) 8:(-s,s),   s = c2/sqrt(2)
  * Element (i, y, x) is at  f[i*pitch*ny + y*pitch + x]  (x fastest, pitch >= nx,
  * pitch a multiple of 64 elements, base pointer 256-byte aligned; the step
- * writes unspecified values into the padding columns nx <= x < pitch, and no
- * entry point reads them as data). Site (x, y)
+ * and the adjoint step write unspecified values into the padding columns
+ * nx <= x < pitch, and no entry point reads them as data). Site (x, y)
  * has centre ((x+0.5) dx, (y+0.5) dx). Macroscopic fields (rho, ux, uy, p or T)
  * are dense row-major (ny, nx) float64 arrays.
  *

@@ -502,6 +502,15 @@ __device__ __forceinline__ void march(const KTConsts& K, const View<S>& fi, cons
   fi.load9((uint32_t)y0 * fi.rowB + L.vbx, cd);
   load_raw9(fi, (uint32_t)y0 * fi.rowB + L.vbh, H0);
   load_raw9(fi, (uint32_t)min(y0 + 1, ny - 1) * fi.rowB + L.vbx, N0);
+  // Float storage: let the prologue's fetches land before the loop, so that the
+  // loop header sees only the previous iteration's fetches in flight and the
+  // compiler's wait counts there need not cover the prologue's loads on the
+  // entry edge (which otherwise drain every fetch and store each iteration).
+  // Double storage schedules well without it and keeps more registers.
+  if constexpr (sizeof(S) == 4) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(pd[i]), "v"(cd[i]), "v"(N0[i]), "v"(H0[i]));
+  }
   // Rows below ylast have a real upper neighbour; ylast is also the last row
   // fetched (the upper neighbour of row y1-1, unless that is the ghost).
   const int ylast = min(y1, ny - 1);
@@ -711,7 +720,7 @@ __device__ __forceinline__ void adj_row(const KTConsts& K, const View<double>& g
                                         bool pery) {
   double fc[9], acc[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) fc[i] = (double)fr[i];
+  for (int i = 0; i < 9; ++i) fc[i] = widen(fr[i]);
   const Prim P = moments9(K, fc);
   collision_adjoint(K, P, gc, acc);
   const int x = L.x, nx = K.nx;
@@ -736,13 +745,52 @@ __device__ __forceinline__ void adj_row(const KTConsts& K, const View<double>& g
   }
   if (y == 0 && !pery) adj_edge<2>(K, gc, x, acc);
   if (y == K.ny - 1 && !pery) adj_edge<3>(K, gc, x, acc);
-  if (x < nx) go.store9((uint32_t)y * go.rowB + vbg, acc);
+  go.store9((uint32_t)y * go.rowB + vbg, acc);   // padding lanes too (see row_update)
 }
 
-// Adjoint march over a 64-column wavefront strip, the same structure as the
-// forward march: g_{n+1} rows y-1, y, y+1 in registers, row y+2 and the f_n row
-// y+1 fetched one iteration ahead, x-neighbours through DPP shifts with the two
-// halo columns read by lanes 0 and 63.
+// One row y < ny-1 of the adjoint march (the same pipeline as march_row): issue
+// the fetches of g_{n+1} row y+2 (into F), of f_n row y+1 (into FN) and of the
+// g_{n+1} halo of row y+1 (into HN), all unconditional with clamped rows;
+// update row y; shift gd <- gc <- row y+1.
+template <bool XEDGE, typename S>
+__device__ __forceinline__ void adj_march_row(const KTConsts& K, const View<S>& ff, const View<double>& gi,
+                                              const View<double>& go, const Lane& L, uint32_t vbf, int y, int y1,
+                                              int ylast, bool perx, bool pery, double pd[9], double cd[9],
+                                              const double N[9], const double HC[9], const S FC[9], double F[9],
+                                              double HN[9], S FN[9]) {
+  load_raw9(gi, (uint32_t)min(y + 2, ylast) * gi.rowB + L.vbx, F);
+  load_raw9(ff, (uint32_t)min(y + 1, y1 - 1) * ff.rowB + vbf, FN);
+  load_raw9(gi, (uint32_t)min(y + 1, y1 - 1) * gi.rowB + L.vbh, HN);
+  adj_row<XEDGE>(K, gi, go, L, L.vbx, y, pd, cd, N, HC, FC, perx, pery);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    pd[i] = cd[i];
+    cd[i] = N[i];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Row y = ny-1 of the adjoint march: above it lies row 0 (periodic) or nothing.
+template <bool XEDGE, typename S>
+__device__ __forceinline__ void adj_top_row(const KTConsts& K, const View<S>& ff, const View<double>& gi,
+                                            const View<double>& go, const Lane& L, int y, bool perx, bool pery,
+                                            const double pd[9], const double cd[9], const double HC[9],
+                                            const S FC[9]) {
+  double nd[9];
+  if (pery) {
+    gi.load9(L.vbx, nd);   // row 0
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) nd[i] = 0.0;
+  }
+  adj_row<XEDGE>(K, gi, go, L, L.vbx, y, pd, cd, nd, HC, FC, perx, pery);
+}
+
+// Adjoint march over a 64-column wavefront strip with the structure of the
+// forward march: g_{n+1} rows y-1, y, y+1 in registers, row y+2, the f_n row
+// y+1 and the halo of row y+1 fetched one row ahead into the idle one of two
+// register sets, x-neighbours through DPP shifts (lanes 0 and 63 use the halo
+// columns), the top row of the grid after the loop.
 template <bool XEDGE, typename S>
 __device__ __forceinline__ void adj_march(const KTConsts& K, const View<S>& ff, const View<double>& gi,
                                           const View<double>& go, int xw0, int lane, int y0, int y1) {
@@ -750,8 +798,8 @@ __device__ __forceinline__ void adj_march(const KTConsts& K, const View<S>& ff, 
   const bool perx = (K.kind[0] == BC_PERIODIC), pery = (K.kind[2] == BC_PERIODIC);
   const Lane L = make_lane<double>(K, xw0, lane);
   const uint32_t vbf = (uint32_t)L.x * sizeof(S);
-  double pd[9], cd[9], nd[9], N[9], F[9], HC[9], HN[9];
-  S FC[9], FN[9];
+  double pd[9], cd[9], N0[9], N1[9], H0[9], H1[9];
+  S FC0[9], FC1[9];
   if (y0 > 0)
     gi.load9((uint32_t)(y0 - 1) * gi.rowB + L.vbx, pd);
   else if (pery)
@@ -761,36 +809,23 @@ __device__ __forceinline__ void adj_march(const KTConsts& K, const View<S>& ff, 
     for (int i = 0; i < 9; ++i) pd[i] = 0.0;
   }
   gi.load9((uint32_t)y0 * gi.rowB + L.vbx, cd);
+  load_raw9(gi, (uint32_t)y0 * gi.rowB + L.vbh, H0);
+  load_raw9(gi, (uint32_t)min(y0 + 1, ny - 1) * gi.rowB + L.vbx, N0);
+  load_raw9(ff, (uint32_t)y0 * ff.rowB + vbf, FC0);
+  // the prologue's fetches land before the loop (see march)
 #pragma unroll
-  for (int i = 0; i < 9; ++i) HC[i] = 0.0;
-  if (L.halo) load_raw9(gi, (uint32_t)y0 * gi.rowB + L.vbh, HC);
-  if (y0 + 1 < ny) load_raw9(gi, (uint32_t)(y0 + 1) * gi.rowB + L.vbx, N);
-  load_raw9(ff, (uint32_t)y0 * ff.rowB + vbf, FC);
+  for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(pd[i]), "v"(cd[i]), "v"(N0[i]), "v"(H0[i]), "v"(FC0[i]));
   const int ylast = min(y1, ny - 1);
-  for (int y = y0; y < y1; ++y) {
-    if (y + 2 <= ylast) load_raw9(gi, (uint32_t)(y + 2) * gi.rowB + L.vbx, F);
-    if (y + 1 < y1) load_raw9(ff, (uint32_t)(y + 1) * ff.rowB + vbf, FN);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) HN[i] = 0.0;
-    if (L.halo && y + 1 < y1) load_raw9(gi, (uint32_t)(y + 1) * gi.rowB + L.vbh, HN);
-    if (y + 1 < ny) {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) nd[i] = N[i];
-    } else if (pery) {
-      gi.load9(L.vbx, nd);   // row 0
-    } else {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) nd[i] = 0.0;
-    }
-    adj_row<XEDGE>(K, gi, go, L, L.vbx, y, pd, cd, nd, HC, FC, perx, pery);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      pd[i] = cd[i];
-      cd[i] = nd[i];
-      N[i] = F[i];
-      HC[i] = HN[i];
-      FC[i] = FN[i];
-    }
+  int y = y0;
+  for (; y + 1 < ylast; y += 2) {
+    adj_march_row<XEDGE>(K, ff, gi, go, L, vbf, y, y1, ylast, perx, pery, pd, cd, N0, H0, FC0, N1, H1, FC1);
+    adj_march_row<XEDGE>(K, ff, gi, go, L, vbf, y + 1, y1, ylast, perx, pery, pd, cd, N1, H1, FC1, N0, H0, FC0);
+  }
+  if (y < ylast) {
+    adj_march_row<XEDGE>(K, ff, gi, go, L, vbf, y, y1, ylast, perx, pery, pd, cd, N0, H0, FC0, N1, H1, FC1);
+    if (y + 1 < y1) adj_top_row<XEDGE>(K, ff, gi, go, L, y + 1, perx, pery, pd, cd, H1, FC1);
+  } else if (y < y1) {
+    adj_top_row<XEDGE>(K, ff, gi, go, L, y, perx, pery, pd, cd, H0, FC0);
   }
 }
 
