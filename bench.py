@@ -183,9 +183,84 @@ def bench_batched(dev, steps=2000, nprob=256):
                     raise RuntimeError("batched result differs from the single-problem run (problem %d)" % k)
         B.close()
     sites = sum(g.nx * g.ny for g in grids)
+    mlups = sites * steps / (t_batch * 1e-3) / 1e6
     return {"problems": nprob, "steps": steps, "sites": sites, "draws": info,
             "batched_ms": t_batch, "single_sum_ms": t_single, "speedup": t_single / t_batch,
-            "batched_mlups": sites * steps / (t_batch * 1e-3) / 1e6, "nonfinite_problems": nonfinite}
+            "batched_mlups": mlups, "roofline_frac": mlups * 1e6 * BYTES_PER_SITE["f32"] / (HBM_PEAK_GBS * 1e9),
+            "nonfinite_problems": nonfinite}
+
+
+def bench_adjoint_step(dev, fwd_ms, nsteps=20):
+    """One adjoint step (k_adjoint, FP32 f, FP64 g) on the roofline grid, per launch, against the
+    FP32-storage forward step on the same grid: 36 + 72 + 72 = 180 algorithmic bytes per site."""
+    import torch
+    import paper_0706_0405_amd as lb
+    from paper_0706_0405_amd import api
+    from workloads import problems as P
+
+    cfg = P.roofline_grid()
+    g = lb.Grid.from_workload(cfg)
+    rho, ux, uy, p = fields_to(dev, P.init_fields(cfg))
+    s = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(s):
+        f = lb.init(g, rho, ux, uy, p, prec="f32")
+        del rho, ux, uy, p
+        ga = lb.empty(g, "f64", dev)
+        ga.normal_()
+        gb = lb.empty(g, "f64", dev)
+        states = [f] * nsteps
+        api.adjoint_run(g, states, ga, gb, prec="f32")   # warm
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        out = api.adjoint_run(g, states, ga, gb, prec="f32")
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / nsteps
+        finite = bool(torch.isfinite(out[:, :, :g.nx]).all())
+        del f, ga, gb, out, states
+    torch.cuda.empty_cache()
+    sites = g.nx * g.ny
+    achieved = 180 * sites / (ms * 1e-3) / 1e9
+    return {"grid": [g.nx, g.ny], "kernel": "k_adjoint<float>", "ms_per_step": ms,
+            "mlups": sites / (ms * 1e-3) / 1e6, "forward_ms_per_step": fwd_ms, "ratio": ms / fwd_ms,
+            "ratio_by_bytes": 180 / 72, "achieved_gbs": achieved, "roofline_frac": achieved / HBM_PEAK_GBS,
+            "finite": finite}
+
+
+def bench_configs(dev, max_steps=4000):
+    """The paper's small configurations at their own sizes, graph-launched (launch- and
+    cache-bound: every one of them fits in the Infinity Cache)."""
+    import torch
+    import paper_0706_0405_amd as lb
+    from workloads import problems as P
+
+    cases = [("Sod 200x4", P.sod(), "f64"), ("1000:1 Riemann 2000x4", P.ratio1000(), "f64"),
+             ("1000:1 Riemann 2000x4", P.ratio1000(), "f32"),
+             ("regular reflection 300x90", P.regular_reflection(), "f32"),
+             ("double Mach 960x240", P.double_mach(), "f32")]
+    out = []
+    s = torch.cuda.Stream(device=dev)
+    for name, cfg, prec in cases:
+        g = lb.Grid.from_workload(cfg)
+        steps = min(int(cfg["steps"]), max_steps)
+        steps += steps % 2
+        rho, ux, uy, p = fields_to(dev, P.init_fields(cfg))
+        with torch.cuda.stream(s):
+            fa = lb.init(g, rho, ux, uy, p, prec=prec)
+            fb = lb.empty(g, prec, dev)
+            lb.run(g, fa, fb, steps, prec=prec, use_graph=True)   # capture + first replay
+            lb.init(g, rho, ux, uy, p, prec=prec, out=fa)          # same buffers: the graph is reused
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            lb.run(g, fa, fb, steps, prec=prec, use_graph=True)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+        out.append({"case": name, "grid": [g.nx, g.ny], "storage": prec, "steps": steps,
+                    "ms_per_step": ms / steps, "mlups": g.nx * g.ny * steps / (ms * 1e-3) / 1e6})
+    return out
 
 
 def bench_adjoint(dev, steps=2000):
@@ -241,8 +316,14 @@ def cpu_baseline(target_s=15.0):
     t0 = time.perf_counter()
     f = scheme.run(pb, f, n, 1)
     dt = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": pb.nx * pb.ny * n / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": model, "host_threads": os.cpu_count(),
             "sample": "FP64 oracle, %d steps of the same double-Mach problem at the same spacing on a "
                       "%dx%d grid (%.1f s)" % (n, pb.nx, pb.ny, dt)}
 
@@ -292,6 +373,13 @@ def main():
             log(json.dumps(extras["adjoint"]))
         except ImportError as e:
             extras["adjoint"] = {"error": str(e)}
+        if "f32" in res:
+            log("timing one adjoint step on the roofline grid")
+            extras["adjoint_step"] = bench_adjoint_step(dev, res["f32"]["ms_per_step"])
+            log(json.dumps(extras["adjoint_step"]))
+        log("timing the small configurations at their own sizes")
+        extras["configs"] = bench_configs(dev)
+        log(json.dumps(extras["configs"]))
     cpu = None
     if not args.no_cpu:
         log("timing CPU oracle sample")
