@@ -228,6 +228,69 @@ def bench_adjoint_step(dev, fwd_ms, nsteps=20):
             "finite": finite}
 
 
+def bench_vn(dev, alphas=(0.025, 0.05, 0.075, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0.4, 0.45, 0.5), nkx=64):
+    """GPU von Neumann chooser on the 256 batched Riemann problems: for each problem's
+    left, right and two star states, the largest stable alpha = dt c2 / dx among the
+    candidates over 64 x 4 wave vectors of its periodic grid, the problem taking the
+    minimum over its states; the scan rate vs the oracle's eigenvalues on the host."""
+    import math as m
+    import torch
+    from oracle import vonneumann as ovn
+    from paper_0706_0405_amd import vn
+    import paper_0706_0405_amd as lb
+    from workloads import gasdyn, problems as P
+
+    cfgs, _ = P.batched()
+    cases, dts, owner = [], [], []
+    for k, c in enumerate(cfgs):
+        g = lb.Grid.from_workload(c)
+        L, R = c["left"], c["right"]
+        st = gasdyn.riemann_star(g.gamma, (L[0], L[1], L[3]), (R[0], R[1], R[3]))
+        for s in ((L[0], L[1], 0.0, L[3] / L[0]), (R[0], R[1], 0.0, R[3] / R[0]),
+                  (st.rho_l, st.u, 0.0, st.p / st.rho_l), (st.rho_r, st.u, 0.0, st.p / st.rho_r)):
+            cases.append(vn.case(g, s))
+            dts.append([a * g.dx / g.c2 for a in alphas])
+            owner.append(k)
+    kx = torch.arange(nkx, dtype=torch.float64, device=dev) * (2 * m.pi / nkx)
+    kx = kx.repeat_interleave(4).contiguous()
+    ky = (torch.arange(4, dtype=torch.float64, device=dev) * (m.pi / 2)).repeat(nkx).contiguous()
+    vn.max_stable_dt(cases, dts, kx, ky, 1e-9)        # warm (module load, first launch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best = vn.max_stable_dt(cases, dts, kx, ky, 1e-9)
+    t = time.perf_counter() - t0
+    points = len(cases) * len(alphas) * kx.numel()
+    # tolerances: strict (radius <= 1 + 1e-9), and linear growth of at most 2x over the 2000-step run
+    tol_run = m.log(2.0) / 2000
+    best_run = vn.max_stable_dt(cases, dts, kx, ky, tol_run)
+
+    def per_problem(b):
+        per = {}
+        for k, dt, c in zip(owner, b, cases):
+            a = dt * c.c2 / c.dx
+            per[k] = min(per.get(k, a), a)
+        v = sorted(per.values())
+        return {"min": v[0], "median": v[len(v) // 2], "max": v[-1], "at_least_0.1": sum(a >= 0.1 for a in v)}
+    # the oracle on a bounded host sample of the same points
+    sample = [(c, k) for c in range(0, len(cases), 97) for k in range(0, kx.numel(), 37)]
+    t0 = time.perf_counter()
+    js = {}
+    for c, q in sample:
+        cc = cases[c]
+        prm = {"c1": cc.c1, "c2": cc.c2, "eta0": cc.eta0, "gamma": cc.gamma, "tau": cc.tau, "beta": cc.beta,
+               "dt": dts[c][0], "dx": cc.dx, "lam": [cc.lam[i] for i in range(9)]}
+        stt = (cc.rho, cc.ux, cc.uy, cc.T)
+        if c not in js:
+            js[c] = ovn.collision_jacobian(*stt, cc.c1, cc.c2, cc.eta0, cc.gamma)
+        ovn.max_modulus(stt, prm, float(kx[q]), float(ky[q]), js[c])
+    t_cpu = time.perf_counter() - t0
+    return {"problems": len(cfgs), "states_per_problem": 4, "alphas": list(alphas), "wave_vectors": kx.numel(),
+            "points": points, "ms": t * 1e3, "points_per_s": points / t,
+            "cpu_oracle_points_per_s": len(sample) / t_cpu, "cpu_oracle_sample_points": len(sample),
+            "chosen_alpha_strict": per_problem(best), "tol_run": tol_run,
+            "chosen_alpha_growth_2x_over_run": per_problem(best_run)}
+
+
 def bench_configs(dev, max_steps=4000):
     """The paper's small configurations at their own sizes, graph-launched (launch- and
     cache-bound: every one of them fits in the Infinity Cache)."""
@@ -377,6 +440,9 @@ def main():
             log("timing one adjoint step on the roofline grid")
             extras["adjoint_step"] = bench_adjoint_step(dev, res["f32"]["ms_per_step"])
             log(json.dumps(extras["adjoint_step"]))
+        log("timing the von Neumann chooser")
+        extras["vn_scan"] = bench_vn(dev)
+        log(json.dumps(extras["vn_scan"]))
         log("timing the small configurations at their own sizes")
         extras["configs"] = bench_configs(dev)
         log(json.dumps(extras["configs"]))

@@ -217,8 +217,58 @@ void lb_batch_destroy(lb_batch* b);
 lb_status lb_autotune(const lb_grid* grid, lb_prec prec, void* f_a, void* f_b, int32_t reps,
                       lb_tile* best, float* best_ms, void* stream);
 
+/* ------------------------------------------------------------ von Neumann scan
+ *
+ * Linear stability of the step about a uniform equilibrium, Sec. 3: a Fourier
+ * perturbation F exp(i k.x) of the 9 distributions at the equilibrium of
+ * (rho, u, T) is multiplied per step by the 9x9 complex matrix
+ *     G(k) = diag(s_i(k)) + (1/tau) d f^eq / d f,
+ * Eqs. (SEC-VON-8), (SEC-VON-9) with the dissipation term of Eq. (SEC-VON-12)
+ * (the "-1" of Eq. (SEC-VON-4) read as -delta_ij; tau general), where s_i(k) is
+ * the Fourier symbol of the linear part of the step for plane i: the same
+ * stencil coefficients the step kernels use, so the scan analyses exactly the
+ * implemented scheme. The scheme is linearly stable at (state, parameters, k)
+ * when the spectral radius max_j |omega_j(k)| does not exceed 1. The
+ * eigenvalues are computed per (case, k) on the GPU: Householder reduction to
+ * Hessenberg form, then single-shift QR with Wilkinson shifts and deflation,
+ * in complex double precision. */
+
+/* One scan case: the uniform state and every parameter G depends on. Edges and
+ * grid sizes play no part (the analysis is for the periodic, unbounded grid). */
+typedef struct {
+  double rho, ux, uy, T;    /* equilibrium state, rho > 0, T > 0 (T = p / rho) */
+  double c1, c2, eta0, gamma;
+  double tau, beta, dt, dx;
+  double lambda[9];         /* as in lb_grid: one value per velocity group */
+} lb_vn_case;
+
+/* Spectral radius of G(k) for every (case, wave vector). cases: host array of
+ * ncases (copied to the device; the call waits for that copy, i.e. it
+ * synchronises `stream` once). kdx, kdy: device float64[nk], the wave vector
+ * times dx (radians; k.dy = kdy, dy = dx). reduce = 0: out is device
+ * float64[ncases * nk], out[c * nk + q] = radius at (case c, k_q); reduce = 1:
+ * out is device float64[ncases], the maximum over q. A case whose QR iteration
+ * does not converge gives NaN (NaN wins the maximum). Errors: LB_EINVAL for
+ * NULL pointers, ncases < 1, nk < 1 or ncases * nk >= 2^31; LB_EPARAM (message
+ * names the case) for parameters lb_validate would reject or a state with
+ * rho <= 0 or T <= 0. */
+lb_status lb_vn_scan(const lb_vn_case* cases, int32_t ncases, const double* kdx, const double* kdy, int32_t nk,
+                     int32_t reduce, double* out, void* stream);
+
+/* Largest stable time step per case among candidates: for each case c (its own
+ * dt ignored) the largest dts[c * ndt + j] such that every candidate
+ * dts[c * ndt + 0 .. j] gives a spectral radius <= 1 + tol over all nk wave
+ * vectors; 0 when the first candidate already fails. dts: host
+ * float64[ncases * ndt], each case's row ascending and > 0. kdx, kdy as in
+ * lb_vn_scan. dt_out: host float64[ncases]. Synchronous (returns after the
+ * scan finished); LB_EINVAL for bad candidates or tol < 0. */
+lb_status lb_vn_max_stable_dt(const lb_vn_case* cases, int32_t ncases, const double* dts, int32_t ndt,
+                              const double* kdx, const double* kdy, int32_t nk, double tol, double* dt_out,
+                              void* stream);
+
 /* ABI self-description for bindings: sizeof(lb_grid) (which = 0), sizeof(lb_edge)
- * (1), sizeof(lb_state) (2), sizeof(lb_tile) (3); -1 for other values. */
+ * (1), sizeof(lb_state) (2), sizeof(lb_tile) (3), sizeof(lb_vn_case) (4); -1 for
+ * other values. */
 int64_t lb_struct_size(int32_t which);
 
 const char* lb_status_str(lb_status s);

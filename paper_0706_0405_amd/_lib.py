@@ -32,6 +32,13 @@ class LbTile(ctypes.Structure):
     _fields_ = [("block_x", c_int32), ("rows", c_int32), ("blocks", c_int32)]
 
 
+class LbVnCase(ctypes.Structure):
+    _fields_ = [("rho", c_double), ("ux", c_double), ("uy", c_double), ("T", c_double),
+                ("c1", c_double), ("c2", c_double), ("eta0", c_double), ("gamma", c_double),
+                ("tau", c_double), ("beta", c_double), ("dt", c_double), ("dx", c_double),
+                ("lam", c_double * 9)]
+
+
 class LbError(RuntimeError):
     def __init__(self, status, name, detail):
         super().__init__("%s (%d): %s" % (name, status, detail))
@@ -67,6 +74,9 @@ _SIGS = {
     "lb_batch_destroy": (None, [c_void_p]),
     "lb_autotune": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, c_void_p, c_int32, POINTER(LbTile),
                               POINTER(c_float), c_void_p]),
+    "lb_vn_scan": (c_int32, [POINTER(LbVnCase), c_int32, c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
+    "lb_vn_max_stable_dt": (c_int32, [POINTER(LbVnCase), c_int32, POINTER(c_double), c_int32, c_void_p, c_void_p,
+                                      c_int32, c_double, POINTER(c_double), c_void_p]),
     "lb_struct_size": (c_int64, [c_int32]),
     "lb_status_str": (c_char_p, [c_int32]),
     "lb_last_error": (c_char_p, []),
@@ -87,8 +97,8 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
-        sizes = [L.lb_struct_size(i) for i in range(4)]
-        want = [ctypes.sizeof(t) for t in (LbGrid, LbEdge, LbState, LbTile)]
+        sizes = [L.lb_struct_size(i) for i in range(5)]
+        want = [ctypes.sizeof(t) for t in (LbGrid, LbEdge, LbState, LbTile, LbVnCase)]
         if sizes != want:
             raise RuntimeError("ABI mismatch between lbkt.h and the ctypes structures: %s vs %s" % (sizes, want))
         _lib = L

@@ -7,8 +7,9 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbkt.so")
-SOURCES = [os.path.join(HERE, "csrc", "lbkt.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", "kt_site.hpp"), os.path.join(ROOT, "include", "lbkt.h")]
+SOURCES = [os.path.join(HERE, "csrc", "lbkt.hip"), os.path.join(HERE, "csrc", "vn.hip")]
+DEPS = SOURCES + [os.path.join(HERE, "csrc", "kt_site.hpp"), os.path.join(HERE, "csrc", "lbkt_internal.hpp"),
+                  os.path.join(ROOT, "include", "lbkt.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -22,6 +22,7 @@
 
 #include "../../include/lbkt.h"
 #include "kt_site.hpp"
+#include "lbkt_internal.hpp"
 
 using namespace lbkt;
 
@@ -193,6 +194,10 @@ static void build_consts(const lb_grid* g, KTConsts* K) {
     }
   }
 }
+
+// Shared with the other translation units of the library (not part of the C ABI).
+void lbkt_build_consts(const lb_grid* g, KTConsts* K) { build_consts(g, K); }
+lb_status lbkt_fail(lb_status s, const std::string& msg) { return fail(s, msg); }
 
 // Number of ghost cells behind a moving shock on edge e at time index `step`:
 // ghost cell i is "behind" when (i + 0.5) dx < x0 + y/tan(angle) + speed t/sin(angle).
@@ -1480,6 +1485,7 @@ extern "C" int64_t lb_struct_size(int32_t which) {
     case 1: return (int64_t)sizeof(lb_edge);
     case 2: return (int64_t)sizeof(lb_state);
     case 3: return (int64_t)sizeof(lb_tile);
+    case 4: return (int64_t)sizeof(lb_vn_case);
   }
   return -1;
 }

@@ -35,6 +35,7 @@ def test_struct_layout_matches_binding():
     assert L.lb_struct_size(1) == ctypes.sizeof(_lib.LbEdge)
     assert L.lb_struct_size(2) == ctypes.sizeof(_lib.LbState)
     assert L.lb_struct_size(3) == ctypes.sizeof(_lib.LbTile)
+    assert L.lb_struct_size(4) == ctypes.sizeof(_lib.LbVnCase)
     assert L.lb_struct_size(9) == -1
 
 
@@ -120,3 +121,44 @@ def test_array_elems():
     g = _grid(nx=100, ny=4).c()
     assert g.pitch == 128
     assert _lib.lib().lb_array_elems(ctypes.byref(g)) == 9 * 128 * 4
+
+
+def _vn_case(**kw):
+    from paper_0706_0405_amd import vn
+    c = vn.case(_grid(), (1.0, 0.1, 0.0, 0.5))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_vn_scan_rejects_bad_arguments_before_launch():
+    """Every check of lb_vn_scan / lb_vn_max_stable_dt happens on the host, before
+    any device call (the k pointers are never dereferenced here)."""
+    L = _lib.lib()
+    k = ctypes.c_void_p(1 << 20)
+    out = ctypes.c_void_p(1 << 21)
+    one = (_lib.LbVnCase * 1)(_vn_case())
+    assert L.lb_vn_scan(one, 0, k, k, 4, 0, out, None) == -1
+    assert L.lb_vn_scan(one, 1, k, k, 0, 0, out, None) == -1
+    assert L.lb_vn_scan(one, 1, None, k, 4, 0, out, None) == -1
+    assert L.lb_vn_scan(one, 1, k, k, 4, 0, None, None) == -1
+    assert L.lb_vn_scan(one, 1 << 16, k, k, 1 << 16, 0, out, None) == -1      # 2^32 points
+    for bad in (dict(rho=0.0), dict(T=-1.0), dict(ux=float("nan")), dict(c2=1.0), dict(c1=1.0, c2=1.0),
+                dict(beta=0.7), dict(tau=0.0), dict(gamma=1.0), dict(dt=-1.0)):
+        two = (_lib.LbVnCase * 2)(_vn_case(), _vn_case(**bad))
+        if "c2" in bad and "c1" not in bad:
+            two[1].c1 = 1.0
+        st = L.lb_vn_scan(two, 2, k, k, 4, 0, out, None)
+        assert st == -2, bad
+        assert b"case 1" in L.lb_last_error(), bad
+    dts = (ctypes.c_double * 3)(0.1, 0.05, 0.2)                                  # not ascending
+    res = (ctypes.c_double * 2)()
+    assert L.lb_vn_max_stable_dt(one, 1, dts, 3, k, k, 4, 1e-12, res, None) == -1
+    two = (_lib.LbVnCase * 2)(_vn_case(), _vn_case())
+    dts = (ctypes.c_double * 4)(0.01, 0.02, 0.03, 0.03)                          # case 1 not ascending
+    assert L.lb_vn_max_stable_dt(two, 2, dts, 2, k, k, 4, 1e-12, res, None) == -1
+    assert b"case 1" in L.lb_last_error()
+    dts = (ctypes.c_double * 2)(0.01, 0.02)
+    assert L.lb_vn_max_stable_dt(one, 1, dts, 2, k, k, 4, -1.0, res, None) == -1
+    assert L.lb_vn_max_stable_dt(one, 1, dts, 0, k, k, 4, 0.0, res, None) == -1
+    assert L.lb_vn_max_stable_dt(one, 1, None, 2, k, k, 4, 0.0, res, None) == -1

@@ -1,0 +1,162 @@
+"""GPU von Neumann scan (lb_vn_scan, lb_vn_max_stable_dt) against the oracle's
+amplification matrix of Sec. 3 (Eqs. (SEC-VON-8), (SEC-VON-9), (SEC-VON-12)) and
+against what the mathematics fixes (k = 0, the Sec. 3 figure claims)."""
+import math
+import os
+import random
+
+import pytest
+import torch
+
+from oracle import vonneumann as ovn
+from tests._util import say
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+# Spectral radius agreement with the oracle (LAPACK eigenvalues of the oracle's
+# G): both are backward stable, |d lambda| <= kappa(lambda) * eps * |G| with
+# |G| <= ~10 here; 1e-11 allows eigenvalue condition numbers up to ~5e3.
+TOL_VN = 1e-11
+
+
+def _vn():
+    from paper_0706_0405_amd import vn
+    return vn
+
+
+def _grid(params):
+    from paper_0706_0405_amd import api
+    return api.Grid(nx=1, ny=1, dx=params["dx"], dt=params["dt"], c1=params["c1"], c2=params["c2"],
+                    eta0=params["eta0"], gamma=params["gamma"], tau=params["tau"], beta=params["beta"],
+                    lam=list(params["lam"]), edges=[])
+
+
+def _random_case(rng):
+    c1 = rng.uniform(0.5, 10.0)
+    c2 = c1 * rng.uniform(1.5, 4.0)
+    eta0 = c1 * rng.uniform(0.8, 3.0)
+    dx = rng.choice([1.0, 0.01])
+    diss = rng.random() < 0.7
+    params = {"c1": c1, "c2": c2, "eta0": eta0, "gamma": rng.choice([1.4, 5.0 / 3.0, 1.2]),
+              "tau": rng.choice([1.0, 2.0, 0.8]), "beta": rng.choice([0.0, 0.1, 0.25, 0.5]),
+              "dt": rng.uniform(0.01, 0.5) * dx / c2, "dx": dx,
+              "lam": ([c1 * dx] + [c1 * dx / 10.0] * 4 + [0.0] * 4) if diss else [0.0] * 9}
+    state = (math.exp(rng.uniform(-2.0, 3.0)), rng.uniform(-0.7, 0.7) * c1, rng.uniform(-0.7, 0.7) * c1,
+             rng.uniform(0.05, 1.0) * c1 * c1 / 2.0)
+    return state, params
+
+
+def _kvec(pairs):
+    kx = torch.tensor([p[0] for p in pairs], dtype=torch.float64, device="cuda")
+    ky = torch.tensor([p[1] for p in pairs], dtype=torch.float64, device="cuda")
+    return kx, ky
+
+
+def test_scan_matches_oracle_amplification():
+    vn = _vn()
+    rng = random.Random(7)
+    cases = [_random_case(rng) for _ in range(40)]
+    ks = [(0.0, 0.0), (math.pi, math.pi), (math.pi, 0.0), (0.3, 0.3), (-1.1, 2.0), (2.7, -0.4), (0.05, 0.0),
+          (1.0, math.pi / 2)]
+    kx, ky = _kvec(ks)
+    say("case vn scan vs oracle", len(cases), "cases x", len(ks), "k")
+    got = vn.scan([vn.case(_grid(p), s) for s, p in cases], kx, ky).cpu()
+    worst = 0.0
+    for c, (s, p) in enumerate(cases):
+        J = ovn.collision_jacobian(*s, p["c1"], p["c2"], p["eta0"], p["gamma"])
+        for q, (a, b) in enumerate(ks):
+            want = ovn.max_modulus(s, p, a, b, J)
+            worst = max(worst, abs(float(got[c, q]) - want))
+            assert abs(float(got[c, q]) - want) <= TOL_VN, (c, q, float(got[c, q]), want)
+    say("max |gpu - oracle|", worst)
+
+
+def test_reduced_scan_is_the_maximum_over_k():
+    vn = _vn()
+    rng = random.Random(3)
+    cases = [vn.case(_grid(p), s) for s, p in (_random_case(rng) for _ in range(17))]
+    kx, ky = vn.modes(24, 5)
+    full = vn.scan(cases, kx, ky)
+    red = vn.scan(cases, kx, ky, reduce=True)
+    assert torch.equal(red, full.max(dim=1).values)
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.0, 2.0])
+def test_radius_at_k0_is_one(tau):
+    """At k = 0 the stencil symbol sums to 1 - 1/tau and the collision Jacobian is a
+    projection onto the 4 conserved moments, so the eigenvalues are 1 (x4) and
+    1 - 1/tau (x5): the radius is max(1, |1 - 1/tau|) = 1 for tau >= 1/2."""
+    vn = _vn()
+    rng = random.Random(11)
+    cases = []
+    for _ in range(20):
+        s, p = _random_case(rng)
+        p["tau"] = tau
+        cases.append(vn.case(_grid(p), s))
+    kx, ky = _kvec([(0.0, 0.0)])
+    r = vn.scan(cases, kx, ky).cpu()
+    assert (r - 1.0).abs().max() <= 1e-13, r
+
+
+def _claims():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "vonneumann_claims.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append(line.split())
+    return rows
+
+
+def test_figure_claims_on_the_gpu():
+    """The Sec. 3 claims (Figs. 2, 5, 6, 7), scanned on the GPU over k = (k, k)."""
+    vn = _vn()
+    kx, ky = vn.diagonal(31)
+    for row in _claims():
+        state = [1.0, 10.0, 0.0, 1.0]
+        kw = {}
+        if row[0] == "fig2":
+            kw["dissipation"] = (row[2] == "on")
+            alpha, expect = float(row[3]), row[4]
+        else:
+            name, val, alpha, expect = row[1], float(row[2]), float(row[3]), row[4]
+            if name == "eta0":
+                kw["eta0"] = val
+            elif name == "T":
+                state[3] = val
+            elif name == "u1":
+                state[1] = val
+        p = ovn.figure_params(alpha=alpha, **kw)
+        m = vn.scan([vn.case(_grid(p), state)], kx, ky)[0].cpu()
+        mx = float(m.max())
+        if expect == "stable":
+            assert mx <= 1 + 1e-9, (row, mx)
+        elif expect == "unstable":
+            assert mx > 1 + 1e-3, (row, mx)
+        else:
+            kmax = float(kx[int(m.argmax())])
+            assert 1 + 1e-4 < mx < 1.05 and abs(kmax - 0.5) < 0.15, (row, mx, kmax)
+
+
+def test_max_stable_dt_matches_oracle_brute_force():
+    vn = _vn()
+    rng = random.Random(5)
+    cases = [_random_case(rng) for _ in range(4)]
+    nx, ny = 12, 4
+    kx, ky = vn.modes(nx, ny)
+    ks = list(zip(kx.cpu().tolist(), ky.cpu().tolist()))
+    tol = 1e-9
+    got = []
+    for s, p in cases:
+        dts = [a * p["dx"] / p["c2"] for a in (0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.4, 0.5, 0.7, 1.0)]
+        got.append(vn.max_stable_dt([vn.case(_grid(p), s)], dts, kx, ky, tol)[0])
+        J = ovn.collision_jacobian(*s, p["c1"], p["c2"], p["eta0"], p["gamma"])
+        want = 0.0
+        for dt in dts:
+            q = dict(p, dt=dt)
+            if max(ovn.max_modulus(s, q, a, b, J) for a, b in ks) <= 1 + tol:
+                want = dt
+            else:
+                break
+        assert got[-1] == want, (s, p, got[-1], want)
+    say("chosen dt", got)
