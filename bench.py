@@ -300,6 +300,7 @@ def bench_configs(dev, max_steps=4000):
 
     cases = [("Sod 200x4", P.sod(), "f64"), ("1000:1 Riemann 2000x4", P.ratio1000(), "f64"),
              ("1000:1 Riemann 2000x4", P.ratio1000(), "f32"),
+             ("Mach-30 Riemann 1200x4", P.mach30(), "f64"),
              ("regular reflection 300x90", P.regular_reflection(), "f32"),
              ("double Mach 960x240", P.double_mach(), "f32")]
     out = []
