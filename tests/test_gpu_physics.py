@@ -52,3 +52,68 @@ def test_regular_reflection_reaches_two_shock_steady_state():
     say("region 3 rho %.4f (theory %.4f) p %.4f (%.4f)" % (r3, s3[0], p3, s3[3]))
     for got, want in ((r2, s2[0]), (p2, s2[3]), (r3, s3[0]), (p3, s3[3])):
         assert abs(got - want) <= 0.05 * want
+
+
+def _rr10_cases(lb, vn, g, dts=None):
+    inflow = (1.0, 10.0, 0.0, 1.0 / 1.4)
+    s2, s3, br = gasdyn.regular_reflection_states(1.4, inflow, 30.0)
+    cases = [vn.case(g, (s[0], s[1], s[2], s[3] / s[0])) for s in (s2, s3)]
+    return s2, s3, br, cases
+
+
+def test_regular_reflection_mach10_at_paper_resolution():
+    """Sec. 4.2 / Fig. 11 at the paper's size: 900 x 300, Mach-10 inflow, 30-degree
+    incident shock, c1,c2,eta0 = 10,20,15, to t = 2.5 (FP32 storage). The time step is
+    chosen by the GPU von Neumann scan (largest alpha = c2 dt/dx among the candidates
+    that is strictly stable at both post-shock states over all modes of the grid); the
+    run must reach a steady state whose plateaus behind the incident and the reflected
+    shock match two-shock theory within 3% in density and pressure."""
+    import paper_0706_0405_amd as lb
+    from paper_0706_0405_amd import vn
+    g0 = lb.Grid.from_workload(P.regular_reflection_paper())
+    s2, s3, br, cases = _rr10_cases(lb, vn, g0)
+    alphas = [0.025, 0.05, 0.075, 0.1, 0.15, 0.2, 0.25, 0.3]
+    kx, ky = vn.modes(g0.nx, g0.ny)
+    dts = vn.max_stable_dt(cases, [a * g0.dx / g0.c2 for a in alphas], kx, ky, 1e-12)
+    alpha = round(min(dts) * g0.c2 / g0.dx, 6)
+    say("scan-chosen alpha", alpha)
+    assert alpha >= 0.05
+    cfg = P.regular_reflection_paper(alpha=alpha)
+    n = cfg["steps"]
+    g, f = gpu_run(cfg, n, "f32")
+    (rho, ux, uy, T), flags = gpu_fields(g, f, "f32")
+    assert int(flags[0]) == 0, flags.tolist()
+    fb = lb.empty(g, "f32", f.device)
+    out = lb.run(g, f.clone(), fb, 100, n0=n, prec="f32")
+    (rho2, _, _, _), _ = gpu_fields(g, out, "f32")
+    resid = float((rho2 - rho).abs().sum() / rho.abs().sum())
+    say("steady residual over 100 steps", resid)
+    assert resid < 1e-8
+    rho, T = rho.cpu().numpy(), T.cpu().numpy()
+    p = rho * T
+    theta = -math.degrees(math.atan2(s2[2], s2[1]))
+    xw = g.ny * g.dx / math.tan(math.radians(30.0))
+    assert (7.5 - xw) * math.tan(math.radians(br - theta)) > 0.45   # (7.5, 0.3) lies below the reflected shock
+    r2, p2 = _patch(rho, 3.0, 2.5, g.dx), _patch(p, 3.0, 2.5, g.dx)
+    r3, p3 = _patch(rho, 7.5, 0.3, g.dx), _patch(p, 7.5, 0.3, g.dx)
+    say("region 2 rho %.4f (%.4f) p %.4f (%.4f); region 3 rho %.4f (%.4f) p %.4f (%.4f)"
+        % (r2, s2[0], p2, s2[3], r3, s3[0], p3, s3[3]))
+    for got, want in ((r2, s2[0]), (p2, s2[3]), (r3, s3[0]), (p3, s3[3])):
+        assert abs(got - want) <= 0.03 * want
+
+
+def test_regular_reflection_mach10_printed_time_step_is_unstable():
+    """The printed dt = 1.5e-4 (alpha = 0.3): the scan finds the post-incident state
+    unstable (radius > 1 + 1e-3) and the run goes non-finite before t = 2.5."""
+    import paper_0706_0405_amd as lb
+    from paper_0706_0405_amd import vn
+    cfg = P.regular_reflection_paper(alpha=0.3)
+    g = lb.Grid.from_workload(cfg)
+    s2, s3, br, cases = _rr10_cases(lb, vn, g)
+    kx, ky = vn.modes(g.nx, g.ny)
+    r = vn.scan(cases, kx, ky, reduce=True).cpu()
+    say("radius at alpha 0.3", r.tolist())
+    assert float(r[0]) > 1 + 1e-3
+    g, f = gpu_run(cfg, cfg["steps"], "f32")
+    _, flags = gpu_fields(g, f, "f32")
+    assert int(flags[0]) & 1, flags.tolist()

@@ -98,22 +98,34 @@ def mach30(nx=1200, ny=4, steps=None, alpha=0.05, beta=0.25, lam0_scale=1.0):
     return cfg
 
 
+def regular_reflection_paper(alpha=0.3, t_end=2.5, seed=0):
+    """The regular reflection at the paper's resolution (Sec. 4.2, Fig. 11): 900 x 300
+    cells of 0.01 (9 x 3), Mach-10 inflow (1, 10, 0, 1/1.4), 30-degree incident shock
+    (top state from the oblique-shock relations, which give the printed
+    (5, 8, -3.4641, 20.7143)), c1,c2,eta0 = 10,20,15, run to t = t_end. The printed
+    dt = 1.5e-4 is alpha = c2 dt/dx = 0.3."""
+    dt = alpha * 0.01 / 20.0
+    return regular_reflection(nx=900, ny=300, steps=int(round(t_end / dt)), mach=10.0, seed=seed,
+                              c=(10.0, 20.0, 15.0), alpha=alpha)
+
+
 def init_riemann(cfg):
     return riemann_fields(cfg, cfg["left"], cfg["right"], cfg["x_disc"])
 
 
-def regular_reflection(nx=300, ny=90, steps=20000, mach=2.9, wave_angle_deg=30.0, seed=0):
+def regular_reflection(nx=300, ny=90, steps=20000, mach=2.9, wave_angle_deg=30.0, seed=0, c=(3.0, 9.0, 5.0),
+                       alpha=0.2):
     """Regular reflection of an oblique shock off the bottom wall (Sec. 4.2).
 
     Left: inflow (1, mach, 0, 1/gamma) (sound speed 1); top: the state behind a
     `wave_angle_deg` oblique shock of that inflow; bottom: reflecting wall;
-    right: supersonic outflow. c1,c2,eta0 = 3,9,5; dt = 0.2 dx/c2.
+    right: supersonic outflow. c1,c2,eta0 = c (3,9,5 by default); dt = alpha dx/c2.
     """
     dx = 0.01
     inflow = (1.0, mach, 0.0, 1.0 / GAMMA)
     top = gasdyn.oblique_shock_state(GAMMA, inflow, wave_angle_deg)
     edges = [_edge("inflow", a=inflow), _edge("outflow"), _edge("wall"), _edge("inflow", a=top)]
-    cfg = _base(nx, ny, dx, 0.2 * dx / 9.0, 3.0, 9.0, 5.0, steps, edges, name="regular_reflection")
+    cfg = _base(nx, ny, dx, alpha * dx / c[1], c[0], c[1], c[2], steps, edges, name="regular_reflection")
     cfg["inflow"], cfg["top"], cfg["seed"] = inflow, top, seed
     cfg["wave_angle_deg"] = wave_angle_deg
     return cfg
