@@ -117,3 +117,56 @@ def test_regular_reflection_mach10_printed_time_step_is_unstable():
     g, f = gpu_run(cfg, cfg["steps"], "f32")
     _, flags = gpu_fields(g, f, "f32")
     assert int(flags[0]) & 1, flags.tolist()
+
+
+def test_double_mach_reflection_to_t_0_15():
+    """Sec. 4.2 / Fig. 12 geometry (960 x 240, Mach-10 shock at 60 degrees to the wall,
+    c1,c2,eta0 = 8,16,10) run to t = 0.15 in FP32 storage at alpha = 0.0125: positive
+    density and temperature everywhere, the incident shock where the exact moving shock
+    is (within 2 cells at three heights), and the undisturbed pre- and post-shock
+    plateaus exact to 1e-3."""
+    import paper_0706_0405_amd as lb
+    cfg = P.double_mach(alpha=0.0125)
+    g0 = lb.Grid.from_workload(cfg)
+    n = int(round(0.15 / g0.dt))
+    say("case double Mach to t = 0.15", n, "steps")
+    g, f = gpu_run(cfg, n, "f32")
+    (rho, ux, uy, T), flags = gpu_fields(g, f, "f32")
+    assert int(flags[0]) == 0, flags.tolist()
+    rho, T = rho.cpu().numpy(), T.cpu().numpy()
+    p = rho * T
+    post, t = cfg["post"], n * g.dt
+    for y in (1.5, 2.0, 2.3):
+        row = rho[int(round(y / g.dx - 0.5))]
+        xs = (np.where(row > 0.5 * (cfg["pre"][0] + post[0]))[0].max() + 1) * g.dx
+        xe = cfg["x0"] + y / math.tan(math.radians(60.0)) + 10.0 * t / math.sin(math.radians(60.0))
+        say("shock at y = %.1f: %.3f (exact %.3f)" % (y, xs, xe))
+        assert abs(xs - xe) <= 2 * g.dx
+    for got, want in ((_patch(rho, 1.0, 2.0, g.dx), post[0]), (_patch(p, 1.0, 2.0, g.dx), post[3]),
+                      (_patch(rho, 8.0, 1.0, g.dx), cfg["pre"][0]), (_patch(p, 8.0, 1.0, g.dx), cfg["pre"][3])):
+        assert abs(got - want) <= 1e-3 * want
+
+
+def test_double_mach_reflection_to_t_0_2_with_c1_above_the_wall_jet():
+    """With the printed c1 = 8 the wall jet behind the Mach stem (|u| up to ~13 and more
+    in its oscillations) outruns c1 and T turns negative at t ~ 0.19 (alpha = 0.0125);
+    Sec. 3 (Fig. 7) finds u > c1 unstable and advises c1 about the largest flow speed.
+    With c1,c2,eta0 = 16,32,20 the same problem runs to t = 0.2 at alpha = 0.05 with
+    positive rho and T and the incident shock within 3 cells of the exact position."""
+    import paper_0706_0405_amd as lb
+    cfg = P.double_mach(alpha=0.05, c=(16.0, 32.0, 20.0))
+    g0 = lb.Grid.from_workload(cfg)
+    n = int(round(0.2 / g0.dt))
+    say("case double Mach c1 = 16 to t = 0.2", n, "steps")
+    g, f = gpu_run(cfg, n, "f32")
+    (rho, ux, uy, T), flags = gpu_fields(g, f, "f32")
+    assert int(flags[0]) == 0, flags.tolist()
+    rho = rho.cpu().numpy()
+    post, t = cfg["post"], n * g.dt
+    say("wall jet max |u|", float(ux[0].abs().max()))
+    for y in (1.5, 2.0, 2.3):
+        row = rho[int(round(y / g.dx - 0.5))]
+        xs = (np.where(row > 0.5 * (cfg["pre"][0] + post[0]))[0].max() + 1) * g.dx
+        xe = cfg["x0"] + y / math.tan(math.radians(60.0)) + 10.0 * t / math.sin(math.radians(60.0))
+        say("shock at y = %.1f: %.3f (exact %.3f)" % (y, xs, xe))
+        assert abs(xs - xe) <= 3 * g.dx   # lambda = c1 dx is twice the printed one: a wider shock

@@ -140,12 +140,12 @@ def init_regular_reflection(cfg):
     return (r * (1.0 + xi), np.full((ny, nx), u), np.full((ny, nx), v), np.full((ny, nx), p))
 
 
-def double_mach(nx=960, ny=240, steps=2000, length=9.6, wall_cells=None, alpha=0.025):
+def double_mach(nx=960, ny=240, steps=2000, length=9.6, wall_cells=None, alpha=0.025, c=(8.0, 16.0, 10.0)):
     """Double Mach reflection (Sec. 4.2, Fig. 12): Mach-10 shock at 60 deg to the wall.
 
     Pre-shock (1.4, 0, 0, 1); post-shock from the normal-shock relations; the
     wall starts `wall_cells` cells from the lower-left corner (20 at dx = 0.01,
-    the same physical offset 0.2 at other resolutions); c1,c2,eta0 = 8,16,10;
+    the same physical offset 0.2 at other resolutions); c1,c2,eta0 = c (8,16,10 printed);
     dt = alpha dx/c2 with alpha = 0.025 (larger alpha lets the reflected shock
     foot at the wall drive T negative: the oracle blows up near step 600 at
     alpha = 0.1 and near step 1500 at alpha = 0.05).
@@ -158,7 +158,7 @@ def double_mach(nx=960, ny=240, steps=2000, length=9.6, wall_cells=None, alpha=0
     edges = [_edge("inflow", a=post), _edge("outflow"),
              _edge("wall", split=split, a=post),
              _edge("shock", a=post, b=pre, x0=x0, angle_deg=60.0, speed=10.0)]
-    cfg = _base(nx, ny, dx, alpha * dx / 16.0, 8.0, 16.0, 10.0, steps, edges, name="double_mach")
+    cfg = _base(nx, ny, dx, alpha * dx / c[1], c[0], c[1], c[2], steps, edges, name="double_mach")
     cfg["pre"], cfg["post"], cfg["x0"] = pre, post, x0
     return cfg
 
