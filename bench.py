@@ -150,6 +150,9 @@ def bench_batched(dev, steps=2000, nprob=256):
                 rho, ux, uy, p = fields_to(dev, P.init_fields(c))
                 lb.init(g, rho, ux, uy, p, prec="f32", out=B.view(fa, k))
 
+        from paper_0706_0405_amd import tuning
+        init_all()
+        block_x = tuning.batch_block_for(B, fa, fb)   # block width chosen by timing (cached per device)
         init_all()
         B.step(fa, fb, steps)           # capture + first replay (untimed)
         init_all()
@@ -184,7 +187,7 @@ def bench_batched(dev, steps=2000, nprob=256):
         B.close()
     sites = sum(g.nx * g.ny for g in grids)
     mlups = sites * steps / (t_batch * 1e-3) / 1e6
-    return {"problems": nprob, "steps": steps, "sites": sites, "draws": info,
+    return {"problems": nprob, "steps": steps, "sites": sites, "draws": info, "block_x": block_x,
             "batched_ms": t_batch, "single_sum_ms": t_single, "speedup": t_single / t_batch,
             "batched_mlups": mlups, "roofline_frac": mlups * 1e6 * BYTES_PER_SITE["f32"] / (HBM_PEAK_GBS * 1e9),
             "nonfinite_problems": nonfinite}

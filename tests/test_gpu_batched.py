@@ -8,7 +8,7 @@ import torch
 from oracle import scheme
 from workloads import problems as P
 
-from tests._util import F64, rel_l1, say
+from tests._util import F64, gpu_run, rel_l1, say
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -108,3 +108,33 @@ def test_batched_against_oracle_fp32_bound():
         e = rel_l1(r[0], R[0])
         say("problem", pick[k], "L", c["nx"], "fast", c["fast"], "rel L1", e)
         assert e < 1e-5
+
+
+def test_autotuners_pick_valid_shapes_and_keep_results(tmp_path, monkeypatch):
+    """lb_autotune (single grid) and the batched block-width tuner return valid launch
+    shapes, cache them, and the tuned shapes give the same bits as the defaults."""
+    import paper_0706_0405_amd as lb
+    from paper_0706_0405_amd import tuning
+    monkeypatch.setattr(tuning, "CACHE", str(tmp_path / "tune.json"))
+    cfg = P.double_mach(nx=333, ny=77)
+    g, f0 = gpu_run(cfg, 0, "f32")
+    fa, fb = f0.clone(), torch.empty_like(f0)
+    tile = tuning.tile_for(g, fa, fb, prec="f32", reps=2)
+    say("tuned tile", tile)
+    assert tile[0] in (64, 128, 256) and tile[1] >= 1
+    assert tuning.tile_for(g, fa, fb, prec="f32") == tile          # from the cache
+    _, ref = gpu_run(cfg, 10, "f32")
+    _, got = gpu_run(cfg, 10, "f32", tile=tile)
+    assert torch.equal(_bits(got[:, :, :g.nx]), _bits(ref[:, :, :g.nx]))
+    cfgs, _ = P.batched(nprob=12, steps=10, screen=False)
+    grids = [lb.Grid.from_workload(c) for c in cfgs]
+    B = lb.Batch(grids, "f32")
+    try:
+        a, b = B.empty(), B.empty()
+        a.zero_()
+        b.zero_()
+        bx = tuning.batch_block_for(B, a, b, steps=4)
+        say("tuned batch block", bx)
+        assert bx in (64, 128, 256)
+    finally:
+        B.close()
