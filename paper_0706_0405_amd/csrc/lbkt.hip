@@ -643,10 +643,32 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 }
 
 // Per-block partial sums of (rho, jx, jy, E) over rows [b*rpb, (b+1)*rpb): fixed order.
+// Sum of v over the 64 lanes of the wavefront (butterfly of lane shuffles; every
+// lane ends with the same total, in a fixed order).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sums of the 4 accumulators over a 256-thread block (4 wavefronts; both callers
+// launch 256 threads): wavefront shuffles, then
+// the 4 wave totals combined in LDS by thread 0..3 (fixed order).
+__device__ __forceinline__ void block_sum4(double acc[4], double* out4) {
+  __shared__ double sh[4][4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[k][wave] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < 4) out4[threadIdx.x] = (sh[threadIdx.x][0] + sh[threadIdx.x][1]) + (sh[threadIdx.x][2] + sh[threadIdx.x][3]);
+}
+
 template <typename S>
 __global__ __launch_bounds__(256) void k_inv_partial(KTConsts K, const S* __restrict__ f, int rpb,
                                                      double* __restrict__ part) {
-  __shared__ double sh[4][256];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const int y0 = blockIdx.x * rpb, y1 = min(y0 + rpb, K.ny);
   for (int y = y0; y < y1; ++y) {
@@ -663,29 +685,14 @@ __global__ __launch_bounds__(256) void k_inv_partial(KTConsts K, const S* __rest
       acc[3] += fma(K.eta0sq, c[0], fma(K.c1sq, s14, K.c2sq * s58));
     }
   }
-  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w)
-      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x < 4) part[(int64_t)blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+  block_sum4(acc, part + (int64_t)blockIdx.x * 4);
 }
 
 __global__ __launch_bounds__(256) void k_inv_final(const double* __restrict__ part, int nblk, double* out4) {
-  __shared__ double sh[4][256];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblk; b += blockDim.x)
     for (int k = 0; k < 4; ++k) acc[k] += part[(int64_t)b * 4 + k];
-  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w)
-      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x < 4) out4[threadIdx.x] = sh[threadIdx.x][0];
+  block_sum4(acc, out4);
 }
 
 // ------------------------------------------------------------------ adjoint
