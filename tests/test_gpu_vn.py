@@ -160,3 +160,49 @@ def test_max_stable_dt_matches_oracle_brute_force():
                 break
         assert got[-1] == want, (s, p, got[-1], want)
     say("chosen dt", got)
+
+
+def test_unstable_parameters_grow_at_the_scanned_rate_and_blow_up():
+    """Failure injection through parameters: Fig. 5's eta0 = 5 (alpha = 0.3, u = 10,
+    T = 1) is linearly unstable. A seeded 1e-10 density perturbation of the uniform
+    state on a 60 x 4 periodic grid must grow at the rate the GPU scan predicts for
+    the grid's modes: the measured growth per step of the density deviation over steps
+    20-40 must not exceed the largest spectral radius (which bounds every mode) and must
+    come within 5% of it (the perturbation still mixes modes of nearby rates), and
+    lb_moments must flag the blow-up within 3x the predicted number of steps to O(1)."""
+    import numpy as np
+    from paper_0706_0405_amd import api
+    vn = _vn()
+    p = ovn.figure_params(alpha=0.3, eta0=5.0)
+    nx, ny = 60, 4
+    edges = [{"kind": "periodic"} for _ in range(4)]
+    g = api.Grid(nx=nx, ny=ny, dx=p["dx"], dt=p["dt"], c1=p["c1"], c2=p["c2"], eta0=p["eta0"],
+                 gamma=p["gamma"], tau=p["tau"], beta=p["beta"], lam=list(p["lam"]), edges=edges)
+    kx, ky = vn.modes(nx, ny)
+    r = float(vn.scan([vn.case(g, (1.0, 10.0, 0.0, 1.0))], kx, ky, reduce=True)[0])
+    delta = 1e-10
+    n_pred = math.log(1.0 / delta) / math.log(r)
+    say("scanned radius", r, "predicted steps to O(1)", n_pred)
+    assert r > 1.1
+    xi = np.random.default_rng(4).uniform(-1.0, 1.0, size=(ny, nx))
+    rho = torch.tensor(1.0 + delta * xi, dtype=torch.float64, device="cuda")
+    ux = torch.full((ny, nx), 10.0, dtype=torch.float64, device="cuda")
+    uy = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    f = api.init(g, rho, ux, uy, rho.clone(), prec="f64")   # T = p / rho = 1
+    buf = api.empty(g, "f64", f.device)
+
+    def amp_after(n, start, n0):
+        out = api.run(g, start, buf, n, n0=n0, prec="f64")
+        r_, _, _, _, fl = api.moments(g, out)
+        return out, float((r_ - r_.mean()).abs().max()), fl.cpu().tolist()
+
+    f20, a20, fl20 = amp_after(20, f, 0)
+    f20 = f20.clone()
+    f40, a40, fl40 = amp_after(20, f20, 20)
+    rate = (a40 / a20) ** (1.0 / 20)
+    say("amplitudes", a20, a40, "growth per step", rate, "flags", fl20, fl40)
+    assert fl40[0] == 0
+    assert 0.95 * r <= rate <= 1.005 * r
+    out, _, fl = amp_after(int(3 * n_pred) - 40 + (int(3 * n_pred) % 2), f40.clone(), 40)
+    say("flags after 3x the predicted steps", fl)
+    assert fl[0] != 0
