@@ -23,7 +23,9 @@
  * and the adjoint step write unspecified values into the padding columns
  * nx <= x < pitch, and no entry point reads them as data). Site (x, y)
  * has centre ((x+0.5) dx, (y+0.5) dx). Macroscopic fields (rho, ux, uy, p or T)
- * are dense row-major (ny, nx) float64 arrays.
+ * are dense row-major (ny, nx) float64 arrays. Sizes: pitch <= 2^27 elements,
+ * nx and ny up to 2^31 - 1; an array may exceed 4 GiB (device memory is the
+ * limit), except one problem of a batch (below 4 GiB).
  *
  * Precision: LB_F64 stores f in float64; LB_F32 stores f in float32 and widens
  * every load to float64, so moments, the division by rho, T, f^eq and the
@@ -118,7 +120,9 @@ typedef struct { int32_t block_x, rows, blocks; } lb_tile;
 /* Fill grid->lambda with Eq. (SEC-VON-13): c1 dx, c1 dx/10 (i = 1..4), 0 (i = 5..8). */
 lb_status lb_default_lambda(lb_grid* grid);
 
-/* Host-only validation of every field of *grid (no GPU needed). */
+/* Host-only validation of every field of *grid (no GPU needed): LB_EINVAL for
+ * sizes and pitch, LB_EPARAM for scheme parameters and edge states,
+ * LB_EUNSUPPORTED for pitch > 2^27 or lambda_1..4 (lambda_5..8) not all equal. */
 lb_status lb_validate(const lb_grid* grid);
 
 /* Number of elements of one distribution array (9 * pitch * ny). */
@@ -192,7 +196,9 @@ lb_status lb_init_adjoint(const lb_grid* grid, const double* rho, const double* 
 typedef struct lb_batch lb_batch;
 
 /* Build a batch from a host array of grids (pitch fields are ignored and
- * recomputed). Uploads per-problem constants and a work list. */
+ * recomputed). Uploads per-problem constants and a work list. Errors as
+ * lb_validate, LB_EUNSUPPORTED for a SHOCK edge or a problem whose array
+ * reaches 4 GiB. */
 lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, lb_prec prec, lb_batch** out);
 
 /* Element offset of each problem's array inside the packed array (host int64[nprob])

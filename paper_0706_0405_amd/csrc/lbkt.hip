@@ -18,6 +18,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/lbkt.h"
@@ -73,8 +74,7 @@ extern "C" lb_status lb_validate(const lb_grid* g) {
   if (g->nx < 1 || g->ny < 1) return fail(LB_EINVAL, "nx and ny must be >= 1");
   if (g->pitch < g->nx || g->pitch % 64 != 0)
     return fail(LB_EINVAL, "pitch must be >= nx and a multiple of 64");
-  if ((double)g->pitch * g->ny * 9.0 * 8.0 >= 4294967296.0)
-    return fail(LB_EUNSUPPORTED, "a distribution array must stay below 4 GiB (9 * pitch * ny * 8 bytes)");
+  if (g->pitch > ((int64_t)1 << 27)) return fail(LB_EUNSUPPORTED, "pitch must be at most 2^27 elements");
   if (!finite_pos(g->dx) || !finite_pos(g->dt)) return fail(LB_EPARAM, "dx and dt must be > 0");
   if (!finite_pos(g->c1) || !finite_pos(g->c2) || !finite_pos(g->eta0))
     return fail(LB_EPARAM, "c1, c2, eta0 must be > 0");
@@ -221,7 +221,8 @@ static int shock_cells(const lb_grid* g, int e, int64_t step) {
 // Distribution arrays are addressed through buffer resources: one 32-bit byte
 // offset per lane (row and column) plus a per-plane scalar offset, so the 9
 // planes share a single address register and out-of-range accesses cannot fault
-// (they read 0 / are dropped by the hardware). Arrays must be below 4 GiB.
+// (they read 0 / are dropped by the hardware). That covers arrays below 4 GiB;
+// larger ones get one resource per plane over the rows a tile touches (ViewG).
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 #define LB_RSRC_WORD3 0x00020000
 // cache policy of the distribution stores: non-temporal (the next step reads
@@ -266,20 +267,38 @@ template <> struct Mem<float> {
   }
 };
 
-// A distribution array viewed through a buffer resource.
+template <typename S>
+__device__ __forceinline__ S ld_raw(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb);
+
+// A distribution array below 4 GiB viewed through a buffer resource. Values are
+// addressed by (plane i, row y, byte offset vb of the column in the row); the
+// row and the column go into the lane's 32-bit offset, the plane into the
+// scalar offset.
 template <typename S>
 struct View {
+  using Sto = S;
   __amdgpu_buffer_rsrc_t r;
   uint32_t rowB;    // bytes per row
   uint32_t planeB;  // bytes per plane
-  __device__ __forceinline__ void load9(uint32_t vb, double v[9]) const {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) v[i] = Mem<S>::ld(r, vb, (uint32_t)i * planeB);
+  __device__ __forceinline__ double ld(int i, int y, uint32_t vb) const {
+    return Mem<S>::ld(r, (uint32_t)y * rowB + vb, (uint32_t)i * planeB);
   }
-  __device__ __forceinline__ void store9(uint32_t vb, const double v[9]) const {
+  __device__ __forceinline__ void load9(int y, uint32_t vb, double v[9]) const {
+    const uint32_t o = (uint32_t)y * rowB + vb;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Mem<S>::st(r, vb, (uint32_t)i * planeB, v[i]);
+    for (int i = 0; i < 9; ++i) v[i] = Mem<S>::ld(r, o, (uint32_t)i * planeB);
   }
+  __device__ __forceinline__ void raw9(int y, uint32_t vb, S v[9]) const {
+    const uint32_t o = (uint32_t)y * rowB + vb;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v[i] = ld_raw<S>(r, o, (uint32_t)i * planeB);
+  }
+  __device__ __forceinline__ void store9(int y, uint32_t vb, const double v[9]) const {
+    const uint32_t o = (uint32_t)y * rowB + vb;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Mem<S>::st(r, o, (uint32_t)i * planeB, v[i]);
+  }
+  __device__ __forceinline__ void load9_any(int y, uint32_t vb, double v[9]) const { load9(y, vb, v); }
 };
 
 template <typename S>
@@ -291,11 +310,67 @@ __device__ __forceinline__ View<S> make_view(const KTConsts& K, const void* p) {
   return v;
 }
 
+// A distribution array of 4 GiB or more, seen by one tile through a window of
+// rows [ylo, yhi]: one buffer resource per plane covering the window's rows
+// (below 4 GiB for any tile), with the interface of View. Rows outside the
+// window (the periodic wrap of the ghost rows) are read through load9_any.
+template <typename S>
+struct ViewG {
+  using Sto = S;
+  __amdgpu_buffer_rsrc_t r[9];
+  const char* base;
+  uint64_t planeB;
+  uint32_t rowB;
+  int ylo;
+  __device__ __forceinline__ uint32_t off(int y, uint32_t vb) const { return (uint32_t)(y - ylo) * rowB + vb; }
+  __device__ __forceinline__ double ld(int i, int y, uint32_t vb) const { return Mem<S>::ld(r[i], off(y, vb), 0); }
+  __device__ __forceinline__ void load9(int y, uint32_t vb, double v[9]) const {
+    const uint32_t o = off(y, vb);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v[i] = Mem<S>::ld(r[i], o, 0);
+  }
+  __device__ __forceinline__ void raw9(int y, uint32_t vb, S v[9]) const {
+    const uint32_t o = off(y, vb);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v[i] = ld_raw<S>(r[i], o, 0);
+  }
+  __device__ __forceinline__ void store9(int y, uint32_t vb, const double v[9]) const {
+    const uint32_t o = off(y, vb);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Mem<S>::st(r[i], o, 0, v[i]);
+  }
+  // any row 0 <= y < ny, inside the window or not (resources made for the row)
+  __device__ __forceinline__ void load9_any(int y, uint32_t vb, double v[9]) const {
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      v[i] = Mem<S>::ld(make_rsrc(base + i * planeB + (uint64_t)(uint32_t)y * rowB, rowB), vb, 0);
+  }
+};
+
+// The window of the tile of rows [y0, y1): rows y0-1 .. y1, clamped into the grid.
+template <typename S>
+__device__ __forceinline__ ViewG<S> make_view_g(const KTConsts& K, const void* p, int y0, int y1) {
+  ViewG<S> v;
+  v.base = (const char*)p;
+  v.rowB = (uint32_t)(K.pitch * sizeof(S));
+  v.planeB = (uint64_t)K.plane * sizeof(S);
+  v.ylo = max(y0 - 1, 0);
+  const int yhi = min(y1, K.ny - 1);
+  const uint32_t bytes = (uint32_t)(yhi - v.ylo + 1) * v.rowB;
+  const char* w = v.base + (uint64_t)(uint32_t)v.ylo * v.rowB;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v.r[i] = make_rsrc(w + i * v.planeB, bytes);
+  return v;
+}
+
+template <class V>
+using Sto = typename V::Sto;
+
 // Ghost row of y edge E (2: below row 0, 3: above row ny-1) at column x
 // (vbx = x * sizeof(S)). Edge indices are compile-time constants so no per-lane
 // indexing of K occurs.
-template <int E, typename S>
-__device__ __forceinline__ void ghost_row(const KTConsts& K, const View<S>& f, int x, uint32_t vbx, int ish,
+template <int E, class V>
+__device__ __forceinline__ void ghost_row(const KTConsts& K, const V& f, int x, uint32_t vbx, int ish,
                                           double r[9]) {
   const int kind = K.kind[E];
   if (kind == BC_PERIODIC || kind == BC_OUTFLOW || kind == BC_WALL) {
@@ -305,7 +380,7 @@ __device__ __forceinline__ void ghost_row(const KTConsts& K, const View<S>& f, i
     else
       src = (E == 2) ? 0 : K.ny - 1;
     double t[9];
-    f.load9((uint32_t)src * f.rowB + vbx, t);
+    f.load9_any(src, vbx, t);
     if (kind == BC_WALL) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) r[i] = t[mirror_y(i)];
@@ -325,8 +400,6 @@ __device__ __forceinline__ void ghost_row(const KTConsts& K, const View<S>& f, i
 }
 
 // Raw storage-typed loads (no widening) for rows held in flight.
-template <typename S>
-__device__ __forceinline__ S ld_raw(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb);
 template <>
 __device__ __forceinline__ double ld_raw<double>(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vb, (int)sb, LB_LOAD_AUX));
@@ -334,12 +407,6 @@ __device__ __forceinline__ double ld_raw<double>(__amdgpu_buffer_rsrc_t r, uint3
 template <>
 __device__ __forceinline__ float ld_raw<float>(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vb, (int)sb, LB_LOAD_AUX));
-}
-
-template <typename S>
-__device__ __forceinline__ void load_raw9(const View<S>& f, uint32_t vb, S v[9]) {
-#pragma unroll
-  for (int i = 0; i < 9; ++i) v[i] = ld_raw<S>(f.r, vb, (uint32_t)i * f.planeB);
 }
 
 // Wavefront lane shifts (DPP wave_shr:1 / wave_shl:1): lane i receives lane
@@ -390,8 +457,8 @@ __device__ __forceinline__ Lane make_lane(const KTConsts& K, int xw0, int lane) 
 }
 
 // Ghost of x edge E for site (x, y) where the shifted neighbour is not the ghost.
-template <int E, typename S>
-__device__ __forceinline__ void ghost_x(const KTConsts& K, const View<S>& f, int y, const double cur[9],
+template <int E, class V>
+__device__ __forceinline__ void ghost_x(const KTConsts& K, const V& f, int y, const double cur[9],
                                         double g[9]) {
   const int kind = K.kind[E];
   if (kind == BC_WALL) {
@@ -405,7 +472,7 @@ __device__ __forceinline__ void ghost_x(const KTConsts& K, const View<S>& f, int
     for (int i = 0; i < 9; ++i) g[i] = cur[i];
   } else {  // periodic: the opposite column
     const int src = (E == 0) ? K.nx - 1 : 0;
-    f.load9((uint32_t)y * f.rowB + (uint32_t)src * sizeof(S), g);
+    f.load9(y, (uint32_t)src * sizeof(Sto<V>), g);
   }
   if (y < K.split[E]) {
 #pragma unroll
@@ -427,10 +494,10 @@ __device__ __forceinline__ double widen(float v) {
 
 // Site update of row y for one lane: prev/cur/nxt are the rows y-1, y, y+1 at
 // the lane's column, hc the halo values of row y (lanes 0 and 63).
-template <bool XEDGE, typename S>
-__device__ __forceinline__ void row_update(const KTConsts& K, const View<S>& fi, const View<S>& fo, const Lane& L,
-                                           int y, const double prev[9], const double cur[9], const double nxt[9],
-                                           const S hc[9]) {
+template <bool XEDGE, class V>
+__device__ __forceinline__ void row_update(const KTConsts& K, const V& fi, const V& fo, const Lane& L, int y,
+                                           const double prev[9], const double cur[9], const double nxt[9],
+                                           const Sto<V> hc[9]) {
   double xm[9], xp[9], out[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -446,7 +513,7 @@ __device__ __forceinline__ void row_update(const KTConsts& K, const View<S>& fi,
   // Lanes past nx store too, into the row's padding columns (x < pitch): no
   // result reads them, and an unmasked store keeps the compiler's wait counts
   // from having to cover a path on which the stores were skipped.
-  fo.store9((uint32_t)y * fi.rowB + L.vbx, out);
+  fo.store9(y, L.vbx, out);
 }
 
 // One row y < ny-1 of the march: issue the fetches of row y+2 (into F) and of
@@ -455,12 +522,12 @@ __device__ __forceinline__ void row_update(const KTConsts& K, const View<S>& fi,
 // lane on every row, the row clamped into the chunk (a clamped fetch repeats
 // one already made and is served from cache): fetches that are always issued
 // let the compiler count them exactly instead of waiting for them early.
-template <bool XEDGE, typename S>
-__device__ __forceinline__ void march_row(const KTConsts& K, const View<S>& fi, const View<S>& fo, const Lane& L,
-                                          int y, int y1, int ylast, double pd[9], double cd[9], const S N[9],
-                                          const S HC[9], S F[9], S HN[9]) {
-  load_raw9(fi, (uint32_t)min(y + 2, ylast) * fi.rowB + L.vbx, F);
-  load_raw9(fi, (uint32_t)min(y + 1, y1 - 1) * fi.rowB + L.vbh, HN);
+template <bool XEDGE, class V>
+__device__ __forceinline__ void march_row(const KTConsts& K, const V& fi, const V& fo, const Lane& L, int y,
+                                          int y1, int ylast, double pd[9], double cd[9], const Sto<V> N[9],
+                                          const Sto<V> HC[9], Sto<V> F[9], Sto<V> HN[9]) {
+  fi.raw9(min(y + 2, ylast), L.vbx, F);
+  fi.raw9(min(y + 1, y1 - 1), L.vbh, HN);
   double nd[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) nd[i] = widen(N[i]);
@@ -474,9 +541,9 @@ __device__ __forceinline__ void march_row(const KTConsts& K, const View<S>& fi, 
 }
 
 // Row y = ny-1, whose upper neighbour is the ghost row of the top edge.
-template <bool XEDGE, typename S>
-__device__ __forceinline__ void top_row(const KTConsts& K, const View<S>& fi, const View<S>& fo, const Lane& L,
-                                        int y, int ish_hi, const double pd[9], const double cd[9], const S HC[9]) {
+template <bool XEDGE, class V>
+__device__ __forceinline__ void top_row(const KTConsts& K, const V& fi, const V& fo, const Lane& L, int y,
+                                        int ish_hi, const double pd[9], const double cd[9], const Sto<V> HC[9]) {
   double nd[9];
   ghost_row<3>(K, fi, L.x, L.vbx, ish_hi, nd);
   row_update<XEDGE>(K, fi, fo, L, y, pd, cd, nd, HC);
@@ -493,20 +560,21 @@ __device__ __forceinline__ void top_row(const KTConsts& K, const View<S>& fi, co
 // is updated after the loop, keeping the ghost's loads and branches out of it.
 // Every lane runs the whole march (the DPP shifts need all lanes); lanes beyond
 // nx compute on padding values and store into the padding.
-template <bool XEDGE, typename S>
-__device__ __forceinline__ void march(const KTConsts& K, const View<S>& fi, const View<S>& fo, const Lane& L,
-                                      int y0, int y1, int ish_lo, int ish_hi) {
+template <bool XEDGE, class V>
+__device__ __forceinline__ void march(const KTConsts& K, const V& fi, const V& fo, const Lane& L, int y0, int y1,
+                                      int ish_lo, int ish_hi) {
+  using S = Sto<V>;
   const int ny = K.ny;
   double pd[9], cd[9];
   S N0[9], N1[9], H0[9], H1[9];
   // prologue: row y0-1 (or the bottom ghost), row y0 and its halo, row y0+1
   if (y0 > 0)
-    fi.load9((uint32_t)(y0 - 1) * fi.rowB + L.vbx, pd);
+    fi.load9(y0 - 1, L.vbx, pd);
   else
     ghost_row<2>(K, fi, L.x, L.vbx, ish_lo, pd);
-  fi.load9((uint32_t)y0 * fi.rowB + L.vbx, cd);
-  load_raw9(fi, (uint32_t)y0 * fi.rowB + L.vbh, H0);
-  load_raw9(fi, (uint32_t)min(y0 + 1, ny - 1) * fi.rowB + L.vbx, N0);
+  fi.load9(y0, L.vbx, cd);
+  fi.raw9(y0, L.vbh, H0);
+  fi.raw9(min(y0 + 1, ny - 1), L.vbx, N0);
   // Float storage: let the prologue's fetches land before the loop, so that the
   // loop header sees only the previous iteration's fetches in flight and the
   // compiler's wait counts there need not cover the prologue's loads on the
@@ -551,11 +619,12 @@ __device__ __forceinline__ void tile_of_block(int id, int nstrips, int nblocks, 
 // Blocks loop over tile ids id = blockIdx.x, blockIdx.x + gridDim.x, ... (one
 // tile per block when gridDim.x equals the tile count). gridDim.x is a multiple
 // of 8 whenever xcd_map is set, so every tile of a block stays in its XCD's band.
-template <typename S>
+// WIDE: arrays of 4 GiB and more, addressed through ViewG (64-bit addresses).
+template <typename S, bool WIDE>
 __global__ __launch_bounds__(256) LB_STEP_ATTR void k_step(KTConsts K, const S* __restrict__ fin,
                                                            S* __restrict__ fout, int rows, int nstrips, int ntiles,
                                                            int xcd_map, int ish_lo, int ish_hi) {
-  const View<S> fi = make_view<S>(K, fin), fo = make_view<S>(K, fout);
+  const View<S> fi0 = make_view<S>(K, fin), fo0 = make_view<S>(K, fout);
   const int lane = threadIdx.x & 63;
   for (int id = blockIdx.x; id < ntiles; id += gridDim.x) {
     int strip, chunk;
@@ -565,10 +634,18 @@ __global__ __launch_bounds__(256) LB_STEP_ATTR void k_step(KTConsts K, const S* 
     const int y0 = chunk * rows;
     const int y1 = min(y0 + rows, K.ny);
     const Lane L = make_lane<S>(K, xw0, lane);
-    if (xw0 == 0 || xw0 + 64 >= K.nx)
-      march<true>(K, fi, fo, L, y0, y1, ish_lo, ish_hi);
-    else
-      march<false>(K, fi, fo, L, y0, y1, ish_lo, ish_hi);
+    if constexpr (WIDE) {
+      const ViewG<S> fi = make_view_g<S>(K, fin, y0, y1), fo = make_view_g<S>(K, fout, y0, y1);
+      if (xw0 == 0 || xw0 + 64 >= K.nx)
+        march<true>(K, fi, fo, L, y0, y1, ish_lo, ish_hi);
+      else
+        march<false>(K, fi, fo, L, y0, y1, ish_lo, ish_hi);
+    } else {
+      if (xw0 == 0 || xw0 + 64 >= K.nx)
+        march<true>(K, fi0, fo0, L, y0, y1, ish_lo, ish_hi);
+      else
+        march<false>(K, fi0, fo0, L, y0, y1, ish_lo, ish_hi);
+    }
   }
 }
 
@@ -725,11 +802,10 @@ __device__ __forceinline__ void adj_edge(const KTConsts& K, const double gc[9], 
 // y+1 (gu) (zero where a non-periodic edge has no such row), the halo values hc
 // of row y and f_n at the site. Accumulation order: collision adjoint, then
 // the y+1, y-1, x+1, x-1 and centre terms, then the own-ghost corrections.
-template <bool XEDGE, typename S>
-__device__ __forceinline__ void adj_row(const KTConsts& K, const View<double>& gi, const View<double>& go,
-                                        const Lane& L, uint32_t vbg, int y, const double gd[9], const double gc[9],
-                                        const double gu[9], const double hc[9], const S fr[9], bool perx,
-                                        bool pery) {
+template <bool XEDGE, class VG, typename S>
+__device__ __forceinline__ void adj_row(const KTConsts& K, const VG& gi, const VG& go, const Lane& L, uint32_t vbg,
+                                        int y, const double gd[9], const double gc[9], const double gu[9],
+                                        const double hc[9], const S fr[9], bool perx, bool pery) {
   double fc[9], acc[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) fc[i] = widen(fr[i]);
@@ -742,7 +818,7 @@ __device__ __forceinline__ void adj_row(const KTConsts& K, const View<double>& g
     double gl = shr1(hc[i], gc[i]);   // g_{n+1}(x-1): site x is its x+dx neighbour
     if (XEDGE) {
       if (x == 0 && !perx) gl = 0.0;
-      if (x == nx - 1) gr = perx ? Mem<double>::ld(gi.r, (uint32_t)y * gi.rowB, (uint32_t)i * gi.planeB) : 0.0;
+      if (x == nx - 1) gr = perx ? gi.ld(i, y, 0) : 0.0;
     }
     double a = acc[i];
     a = fma(wcoef(K, i, 4), gu[i], a);
@@ -757,22 +833,22 @@ __device__ __forceinline__ void adj_row(const KTConsts& K, const View<double>& g
   }
   if (y == 0 && !pery) adj_edge<2>(K, gc, x, acc);
   if (y == K.ny - 1 && !pery) adj_edge<3>(K, gc, x, acc);
-  go.store9((uint32_t)y * go.rowB + vbg, acc);   // padding lanes too (see row_update)
+  go.store9(y, vbg, acc);   // padding lanes too (see row_update)
 }
 
 // One row y < ny-1 of the adjoint march (the same pipeline as march_row): issue
 // the fetches of g_{n+1} row y+2 (into F), of f_n row y+1 (into FN) and of the
 // g_{n+1} halo of row y+1 (into HN), all unconditional with clamped rows;
 // update row y; shift gd <- gc <- row y+1.
-template <bool XEDGE, typename S>
-__device__ __forceinline__ void adj_march_row(const KTConsts& K, const View<S>& ff, const View<double>& gi,
-                                              const View<double>& go, const Lane& L, uint32_t vbf, int y, int y1,
-                                              int ylast, bool perx, bool pery, double pd[9], double cd[9],
-                                              const double N[9], const double HC[9], const S FC[9], double F[9],
-                                              double HN[9], S FN[9]) {
-  load_raw9(gi, (uint32_t)min(y + 2, ylast) * gi.rowB + L.vbx, F);
-  load_raw9(ff, (uint32_t)min(y + 1, y1 - 1) * ff.rowB + vbf, FN);
-  load_raw9(gi, (uint32_t)min(y + 1, y1 - 1) * gi.rowB + L.vbh, HN);
+template <bool XEDGE, class VF, class VG>
+__device__ __forceinline__ void adj_march_row(const KTConsts& K, const VF& ff, const VG& gi, const VG& go,
+                                              const Lane& L, uint32_t vbf, int y, int y1, int ylast, bool perx,
+                                              bool pery, double pd[9], double cd[9], const double N[9],
+                                              const double HC[9], const Sto<VF> FC[9], double F[9], double HN[9],
+                                              Sto<VF> FN[9]) {
+  gi.raw9(min(y + 2, ylast), L.vbx, F);
+  ff.raw9(min(y + 1, y1 - 1), vbf, FN);
+  gi.raw9(min(y + 1, y1 - 1), L.vbh, HN);
   adj_row<XEDGE>(K, gi, go, L, L.vbx, y, pd, cd, N, HC, FC, perx, pery);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -783,14 +859,13 @@ __device__ __forceinline__ void adj_march_row(const KTConsts& K, const View<S>& 
 }
 
 // Row y = ny-1 of the adjoint march: above it lies row 0 (periodic) or nothing.
-template <bool XEDGE, typename S>
-__device__ __forceinline__ void adj_top_row(const KTConsts& K, const View<S>& ff, const View<double>& gi,
-                                            const View<double>& go, const Lane& L, int y, bool perx, bool pery,
-                                            const double pd[9], const double cd[9], const double HC[9],
-                                            const S FC[9]) {
+template <bool XEDGE, class VF, class VG>
+__device__ __forceinline__ void adj_top_row(const KTConsts& K, const VF& ff, const VG& gi, const VG& go,
+                                            const Lane& L, int y, bool perx, bool pery, const double pd[9],
+                                            const double cd[9], const double HC[9], const Sto<VF> FC[9]) {
   double nd[9];
   if (pery) {
-    gi.load9(L.vbx, nd);   // row 0
+    gi.load9_any(0, L.vbx, nd);   // row 0
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) nd[i] = 0.0;
@@ -803,9 +878,10 @@ __device__ __forceinline__ void adj_top_row(const KTConsts& K, const View<S>& ff
 // y+1 and the halo of row y+1 fetched one row ahead into the idle one of two
 // register sets, x-neighbours through DPP shifts (lanes 0 and 63 use the halo
 // columns), the top row of the grid after the loop.
-template <bool XEDGE, typename S>
-__device__ __forceinline__ void adj_march(const KTConsts& K, const View<S>& ff, const View<double>& gi,
-                                          const View<double>& go, int xw0, int lane, int y0, int y1) {
+template <bool XEDGE, class VF, class VG>
+__device__ __forceinline__ void adj_march(const KTConsts& K, const VF& ff, const VG& gi, const VG& go, int xw0,
+                                          int lane, int y0, int y1) {
+  using S = Sto<VF>;
   const int ny = K.ny;
   const bool perx = (K.kind[0] == BC_PERIODIC), pery = (K.kind[2] == BC_PERIODIC);
   const Lane L = make_lane<double>(K, xw0, lane);
@@ -813,17 +889,17 @@ __device__ __forceinline__ void adj_march(const KTConsts& K, const View<S>& ff, 
   double pd[9], cd[9], N0[9], N1[9], H0[9], H1[9];
   S FC0[9], FC1[9];
   if (y0 > 0)
-    gi.load9((uint32_t)(y0 - 1) * gi.rowB + L.vbx, pd);
+    gi.load9(y0 - 1, L.vbx, pd);
   else if (pery)
-    gi.load9((uint32_t)(ny - 1) * gi.rowB + L.vbx, pd);
+    gi.load9_any(ny - 1, L.vbx, pd);
   else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) pd[i] = 0.0;
   }
-  gi.load9((uint32_t)y0 * gi.rowB + L.vbx, cd);
-  load_raw9(gi, (uint32_t)y0 * gi.rowB + L.vbh, H0);
-  load_raw9(gi, (uint32_t)min(y0 + 1, ny - 1) * gi.rowB + L.vbx, N0);
-  load_raw9(ff, (uint32_t)y0 * ff.rowB + vbf, FC0);
+  gi.load9(y0, L.vbx, cd);
+  gi.raw9(y0, L.vbh, H0);
+  gi.raw9(min(y0 + 1, ny - 1), L.vbx, N0);
+  ff.raw9(y0, vbf, FC0);
   // the prologue's fetches land before the loop (see march)
 #pragma unroll
   for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(pd[i]), "v"(cd[i]), "v"(N0[i]), "v"(H0[i]), "v"(FC0[i]));
@@ -842,7 +918,9 @@ __device__ __forceinline__ void adj_march(const KTConsts& K, const View<S>& ff, 
 }
 
 // g_n = (dS/df)^T g_np1: transposed stencil over g_np1 plus the local collision adjoint.
-template <typename S>
+// WIDE: the adjoint arrays (double) are 4 GiB or more; all three are then
+// addressed through ViewG.
+template <typename S, bool WIDE>
 __global__ __launch_bounds__(256) void k_adjoint(KTConsts K, const S* __restrict__ fn,
                                                  const double* __restrict__ g1, double* __restrict__ g0,
                                                  int rows, int nstrips, int nblocks, int xcd_map) {
@@ -853,12 +931,21 @@ __global__ __launch_bounds__(256) void k_adjoint(KTConsts K, const S* __restrict
   if (xw0 >= K.nx) return;   // whole wavefront beyond the grid
   const int y0 = chunk * rows;
   const int y1 = min(y0 + rows, K.ny);
-  const View<S> ff = make_view<S>(K, fn);
-  const View<double> gi = make_view<double>(K, g1), go = make_view<double>(K, g0);
-  if (xw0 == 0 || xw0 + 64 >= K.nx)
-    adj_march<true>(K, ff, gi, go, xw0, lane, y0, y1);
-  else
-    adj_march<false>(K, ff, gi, go, xw0, lane, y0, y1);
+  if constexpr (WIDE) {
+    const ViewG<S> ff = make_view_g<S>(K, fn, y0, y1);
+    const ViewG<double> gi = make_view_g<double>(K, g1, y0, y1), go = make_view_g<double>(K, g0, y0, y1);
+    if (xw0 == 0 || xw0 + 64 >= K.nx)
+      adj_march<true>(K, ff, gi, go, xw0, lane, y0, y1);
+    else
+      adj_march<false>(K, ff, gi, go, xw0, lane, y0, y1);
+  } else {
+    const View<S> ff = make_view<S>(K, fn);
+    const View<double> gi = make_view<double>(K, g1), go = make_view<double>(K, g0);
+    if (xw0 == 0 || xw0 + 64 >= K.nx)
+      adj_march<true>(K, ff, gi, go, xw0, lane, y0, y1);
+    else
+      adj_march<false>(K, ff, gi, go, xw0, lane, y0, y1);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_init_adjoint(KTConsts K, const double* __restrict__ rho,
@@ -912,6 +999,19 @@ __global__ __launch_bounds__(256) void k_step_batched(const KTConsts* __restrict
 
 static size_t elem_size(lb_prec p) { return p == LB_F32 ? 4 : 8; }
 
+// Arrays of 4 GiB and more exceed a buffer resource's 32-bit range: their
+// kernels address each plane through its own resource over the rows of one
+// tile (the WIDE instantiations).
+static bool wide(const lb_grid* g, size_t esz) {
+  return (uint64_t)lb_array_elems(g) * esz >= (uint64_t)1 << 32;
+}
+
+// Largest tile height whose window (rows + 2 rows of bytes) stays below 4 GiB.
+static int wide_max_rows(const lb_grid* g, size_t esz) {
+  const uint64_t rowB = (uint64_t)g->pitch * esz;
+  return (int)std::min<uint64_t>(0x7fffffff, (((uint64_t)1 << 32) - 1) / rowB - 2);
+}
+
 static lb_status check_ptr(const void* p, const char* what) {
   if (!p) return fail(LB_EINVAL, std::string(what) + " is NULL");
   if (((uintptr_t)p) % 256 != 0) return fail(LB_EINVAL, std::string(what) + " must be 256-byte aligned");
@@ -959,7 +1059,8 @@ static lb_status resolve_tile(const lb_tile* tile, int nx, int ny, Tile* t) {
 
 static lb_status launch_step(const lb_grid* g, const KTConsts& K, lb_prec prec, const void* fin, void* fout,
                              int64_t step, const Tile& t, hipStream_t st) {
-  const int bx = t.bx, rows = t.rows;
+  const bool w = wide(g, elem_size(prec));
+  const int bx = t.bx, rows = w ? std::min(t.rows, wide_max_rows(g, elem_size(prec))) : t.rows;
   const int nstrips = (g->nx + bx - 1) / bx;
   const int nchunks = (g->ny + rows - 1) / rows;
   const int64_t ntiles64 = (int64_t)nstrips * nchunks;
@@ -969,12 +1070,15 @@ static lb_status launch_step(const lb_grid* g, const KTConsts& K, lb_prec prec, 
   int nblocks = ntiles;
   if (t.blocks > 0 && t.blocks < ntiles) nblocks = xcd_map ? std::max(8, t.blocks & ~7) : t.blocks;
   const int ish_lo = shock_cells(g, 2, step), ish_hi = shock_cells(g, 3, step);
-  if (prec == LB_F64)
-    hipLaunchKernelGGL(k_step<double>, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fin, (double*)fout,
-                       rows, nstrips, ntiles, xcd_map, ish_lo, ish_hi);
-  else
-    hipLaunchKernelGGL(k_step<float>, dim3(nblocks), dim3(bx), 0, st, K, (const float*)fin, (float*)fout,
-                       rows, nstrips, ntiles, xcd_map, ish_lo, ish_hi);
+  if (prec == LB_F64) {
+    auto kern = w ? k_step<double, true> : k_step<double, false>;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fin, (double*)fout, rows, nstrips,
+                       ntiles, xcd_map, ish_lo, ish_hi);
+  } else {
+    auto kern = w ? k_step<float, true> : k_step<float, false>;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(bx), 0, st, K, (const float*)fin, (float*)fout, rows, nstrips,
+                       ntiles, xcd_map, ish_lo, ish_hi);
+  }
   HIP_CHECK(hipGetLastError());
   return LB_OK;
 }
@@ -1169,17 +1273,24 @@ static lb_status launch_adjoint(const lb_grid* g, const KTConsts& K, lb_prec pre
                                 double* g0, hipStream_t st) {
   int bx, rows;
   default_tile(g->nx, g->ny, &bx, &rows);
+  const bool w = wide(g, sizeof(double));   // the adjoint arrays are double
   rows = std::min(rows, g->ny);
+  if (w) rows = std::min(rows, wide_max_rows(g, sizeof(double)));
   const int nstrips = (g->nx + bx - 1) / bx;
   const int nchunks = (g->ny + rows - 1) / rows;
-  const int nblocks = nstrips * nchunks;
+  const int64_t nblocks64 = (int64_t)nstrips * nchunks;
+  if (nblocks64 > 0x7fffffff) return fail(LB_EINVAL, "grid too large for one launch");
+  const int nblocks = (int)nblocks64;
   const int xcd_map = (nblocks % 8 == 0) ? 1 : 0;
-  if (prec == LB_F64)
-    hipLaunchKernelGGL(k_adjoint<double>, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fn, g1, g0, rows,
-                       nstrips, nblocks, xcd_map);
-  else
-    hipLaunchKernelGGL(k_adjoint<float>, dim3(nblocks), dim3(bx), 0, st, K, (const float*)fn, g1, g0, rows,
-                       nstrips, nblocks, xcd_map);
+  if (prec == LB_F64) {
+    auto kern = w ? k_adjoint<double, true> : k_adjoint<double, false>;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fn, g1, g0, rows, nstrips, nblocks,
+                       xcd_map);
+  } else {
+    auto kern = w ? k_adjoint<float, true> : k_adjoint<float, false>;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(bx), 0, st, K, (const float*)fn, g1, g0, rows, nstrips, nblocks,
+                       xcd_map);
+  }
   HIP_CHECK(hipGetLastError());
   return LB_OK;
 }
@@ -1318,6 +1429,10 @@ extern "C" lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, lb_pre
     if ((s = lb_validate(&g))) {
       delete b;
       return fail(s, "problem " + std::to_string(p) + ": " + g_last_error);
+    }
+    if (wide(&g, elem_size(prec))) {
+      delete b;
+      return fail(LB_EUNSUPPORTED, "problem " + std::to_string(p) + ": a batched problem's array must stay below 4 GiB");
     }
     for (int e = 0; e < 4; ++e)
       if (g.edge[e].kind == LB_BC_SHOCK) {

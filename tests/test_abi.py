@@ -100,8 +100,18 @@ def test_validate_rejects_layout_and_edges():
     g = Grid.from_workload(cfg).c()
     g.edge[3].b.rho = -1.0                        # bad shock state
     assert _status(g) == -2
-    g = _grid(nx=8192 * 8, ny=2048).c()           # 9 planes over 4 GiB
+    g = _grid(nx=(1 << 27) + 1, ny=1).c()         # pitch beyond 2^27 elements
     assert _status(g) == -7
+    g = _grid(nx=8192 * 8, ny=2048).c()           # 9 planes over 4 GiB: accepted
+    assert _status(g) == 0
+
+
+def test_batched_problem_over_4_gib_rejected():
+    L = _lib.lib()
+    grids = (_lib.LbGrid * 2)(_grid().c(), _grid(nx=8192 * 8, ny=2048).c())
+    out = ctypes.c_void_p()
+    assert L.lb_batch_create(2, grids, 0, ctypes.byref(out)) == -7
+    assert b"4 GiB" in L.lb_last_error() and not out.value
 
 
 def test_alias_and_alignment_rejected_before_launch():
