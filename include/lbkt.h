@@ -114,8 +114,16 @@ typedef struct {
  * blocks = 0 launches one block per tile; blocks > 0 launches that many
  * persistent blocks (rounded down to a multiple of 8), each looping over tiles.
  * All zero (or a NULL tile) = the default: 256 x 32 tiles, one block per tile,
- * shrunk on small grids (rows down to 2, then columns) to give at least 1024 tiles. */
-typedef struct { int32_t block_x, rows, blocks; } lb_tile;
+ * shrunk on small grids (rows down to 2, then columns) to give at least 1024 tiles.
+ * In the two-step pass a wavefront of 64 threads produces 62 columns, so a tile
+ * is block_x / 64 * 62 columns wide. */
+typedef struct {
+  int32_t block_x, rows, blocks;
+  int32_t steps;   /* lb_run only: time steps per pass over the array, 1 or 2; 0 = the
+                      default, 2 (one step per pass when ny < 2). Two steps per pass
+                      keep the intermediate state in registers (temporal blocking):
+                      half the HBM traffic per step, bitwise the result of single steps. */
+} lb_tile;
 
 /* Fill grid->lambda with Eq. (SEC-VON-13): c1 dx, c1 dx/10 (i = 1..4), 0 (i = 5..8). */
 lb_status lb_default_lambda(lb_grid* grid);
@@ -144,8 +152,11 @@ lb_status lb_step_tiled(const lb_grid* grid, lb_prec prec, const void* f_in, voi
                         int64_t step, const lb_tile* tile, void* stream);
 
 /* nsteps ping-pong steps from f_a at time index step0. The result is in f_a when
- * nsteps is even, else in f_b. use_graph != 0 captures the launches in a HIP graph
- * (cached: a repeated call with the same arguments replays it). */
+ * nsteps is even, else in f_b; the other array is left holding an intermediate
+ * state (with two steps per pass, not necessarily that of step nsteps-1).
+ * use_graph != 0 captures the launches in a HIP graph (cached: a repeated call with
+ * the same arguments replays it). Every launch shape and steps setting gives
+ * bitwise the same result. */
 lb_status lb_run(const lb_grid* grid, lb_prec prec, void* f_a, void* f_b, int64_t step0,
                  int32_t nsteps, int32_t use_graph, const lb_tile* tile, void* stream);
 

@@ -29,7 +29,7 @@ class LbGrid(ctypes.Structure):
 
 
 class LbTile(ctypes.Structure):
-    _fields_ = [("block_x", c_int32), ("rows", c_int32), ("blocks", c_int32)]
+    _fields_ = [("block_x", c_int32), ("rows", c_int32), ("blocks", c_int32), ("steps", c_int32)]
 
 
 class LbVnCase(ctypes.Structure):

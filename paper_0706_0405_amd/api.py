@@ -124,12 +124,14 @@ def init(grid: Grid, rho, ux, uy, p, prec="f64", out=None):
     return f
 
 
-def _tile(tile):
-    """(block_x, rows[, blocks]) -> lb_tile; None = the library default."""
-    if tile is None:
+def _tile(tile, steps=0):
+    """(block_x, rows[, blocks]) -> lb_tile; None = the library's default shape.
+    steps: time steps per pass of lb_run (0 = default, 1 or 2)."""
+    if tile is None and not steps:
         return None
-    blocks = int(tile[2]) if len(tile) > 2 else 0
-    return ctypes.byref(LbTile(int(tile[0]), int(tile[1]), blocks))
+    t = tuple(tile) if tile is not None else (0, 0)
+    blocks = int(t[2]) if len(t) > 2 else 0
+    return ctypes.byref(LbTile(int(t[0]), int(t[1]), blocks, int(steps)))
 
 
 def step(grid: Grid, f_in, f_out, n=0, prec="f64", tile=None):
@@ -142,13 +144,14 @@ def step(grid: Grid, f_in, f_out, n=0, prec="f64", tile=None):
     return f_out
 
 
-def run(grid: Grid, f_a, f_b, nsteps, n0=0, prec="f64", use_graph=False, tile=None):
-    """nsteps ping-pong steps; returns the tensor holding the result (lb_run)."""
+def run(grid: Grid, f_a, f_b, nsteps, n0=0, prec="f64", use_graph=False, tile=None, steps_per_pass=0):
+    """nsteps ping-pong steps; returns the tensor holding the result (lb_run).
+    steps_per_pass: 1 = one step per launch, 2 = two (0 = the library default)."""
     pr = _prec(prec)
     _check_f(grid, pr, f_a, "f_a")
     _check_f(grid, pr, f_b, "f_b")
     check(lib().lb_run(ctypes.byref(grid.c()), pr, _ptr(f_a), _ptr(f_b), int(n0), int(nsteps),
-                       1 if use_graph else 0, _tile(tile), _stream(f_a.device)))
+                       1 if use_graph else 0, _tile(tile, steps_per_pass), _stream(f_a.device)))
     return f_a if nsteps % 2 == 0 else f_b
 
 

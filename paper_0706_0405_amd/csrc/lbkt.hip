@@ -347,20 +347,26 @@ struct ViewG {
   }
 };
 
-// The window of the tile of rows [y0, y1): rows y0-1 .. y1, clamped into the grid.
+// The window of rows [ylo, yhi], clamped into the grid.
 template <typename S>
-__device__ __forceinline__ ViewG<S> make_view_g(const KTConsts& K, const void* p, int y0, int y1) {
+__device__ __forceinline__ ViewG<S> make_view_g_rows(const KTConsts& K, const void* p, int ylo, int yhi) {
   ViewG<S> v;
   v.base = (const char*)p;
   v.rowB = (uint32_t)(K.pitch * sizeof(S));
   v.planeB = (uint64_t)K.plane * sizeof(S);
-  v.ylo = max(y0 - 1, 0);
-  const int yhi = min(y1, K.ny - 1);
+  v.ylo = max(ylo, 0);
+  yhi = min(yhi, K.ny - 1);
   const uint32_t bytes = (uint32_t)(yhi - v.ylo + 1) * v.rowB;
   const char* w = v.base + (uint64_t)(uint32_t)v.ylo * v.rowB;
 #pragma unroll
   for (int i = 0; i < 9; ++i) v.r[i] = make_rsrc(w + i * v.planeB, bytes);
   return v;
+}
+
+// The window a one-step tile of rows [y0, y1) reads: rows y0-1 .. y1.
+template <typename S>
+__device__ __forceinline__ ViewG<S> make_view_g(const KTConsts& K, const void* p, int y0, int y1) {
+  return make_view_g_rows<S>(K, p, y0 - 1, y1);
 }
 
 template <class V>
@@ -645,6 +651,293 @@ __global__ __launch_bounds__(256) LB_STEP_ATTR void k_step(KTConsts K, const S* 
         march<true>(K, fi0, fo0, L, y0, y1, ish_lo, ish_hi);
       else
         march<false>(K, fi0, fo0, L, y0, y1, ish_lo, ish_hi);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ two steps per pass
+
+// Two consecutive steps in one pass over the array (temporal blocking): a
+// wavefront marches its rows as in the one-step march, keeps the state after
+// the first step (f1) of rows y-1, y, y+1 in registers instead of storing it,
+// and updates the second step of row y from them. HBM moves the 9 + 9 values
+// of a site once per two steps. f1 is rounded to the storage type exactly as a
+// stored step would be, and every ghost of f1 is formed as the one-step march
+// forms it from the stored f1, so the result is bitwise that of two single
+// steps.
+//
+// Columns: lane j of a wavefront holds column c = X0 - 1 + j; lanes 1..62 (of
+// columns inside the grid) produce the second step, lanes 0 and 63 hold the f1
+// that those lanes' x-neighbours need, so wavefronts start every 62 columns and
+// overlap by two. With a periodic x axis a lane's column wraps into the grid
+// (lane c = -1 holds column nx-1, so f1 there is the wrapped neighbour itself);
+// otherwise the x ghosts of both steps are formed at columns 0 and nx-1 as in
+// the one-step march. Rows: the tile of output rows [y0, y1) computes f1 on rows
+// y0-1 .. y1 (one extra row each side) from f0 rows y0-2 .. y1+1; the y ghosts
+// of f1 outside the grid come from f1 rows 0 / ny-1 (outflow, wall), from
+// constants at the second step's time (inflow, shock), or for a periodic y axis
+// from f1 computed on the far row.
+struct Lane2 {
+  int x;           // column c (may be -1 or >= nx: then only an x-neighbour)
+  int xs;          // the grid column whose values the lane holds (c wrapped or clamped)
+  uint32_t vbx;    // source column (wrapped or clamped into the grid) * sizeof(S)
+  uint32_t vbh;    // halo source column of lanes 0 / 63 * sizeof(S)
+  uint32_t vbo;    // c * sizeof(S) for the output lanes
+  bool out;        // lane produces the second step of its column
+  bool perx;
+};
+
+__device__ __forceinline__ int wrap_col(int c, int nx, bool perx) {
+  return perx ? ((c % nx) + nx) % nx : min(max(c, 0), nx - 1);
+}
+
+template <typename S>
+__device__ __forceinline__ Lane2 make_lane2(const KTConsts& K, int X0, int lane) {
+  Lane2 L;
+  const int nx = K.nx;
+  L.perx = (K.kind[0] == BC_PERIODIC);
+  L.x = X0 - 1 + lane;
+  L.xs = wrap_col(L.x, nx, L.perx);
+  L.vbx = (uint32_t)L.xs * sizeof(S);
+  L.vbh = (uint32_t)wrap_col(lane == 0 ? L.x - 1 : L.x + 1, nx, L.perx) * sizeof(S);
+  L.out = (lane >= 1) && (lane <= 62) && (L.x < nx);
+  L.vbo = L.out ? (uint32_t)L.x * sizeof(S) : 0u;
+  return L;
+}
+
+// f1 of row y at the lane's column from f0 rows y-1, y, y+1 (prev, cur, nxt; hc
+// the halo values of row y), rounded to the storage type.
+template <bool XEDGE, class V>
+__device__ __forceinline__ void row_first(const KTConsts& K, const V& fi, const Lane2& L, int y,
+                                          const double prev[9], const double cur[9], const double nxt[9],
+                                          const Sto<V> hc[9], double t[9]) {
+  double xm[9], xp[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double h = widen(hc[i]);
+    xm[i] = shr1(h, cur[i]);
+    xp[i] = shl1(h, cur[i]);
+  }
+  if (XEDGE && !L.perx) {
+    if (L.x == 0) ghost_x<0>(K, fi, y, cur, xm);
+    if (L.x == K.nx - 1) ghost_x<1>(K, fi, y, cur, xp);
+  }
+  site_update(K, cur, xp, xm, nxt, prev, t);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) t[i] = (double)(Sto<V>)t[i];
+}
+
+// The second step of row y from f1 rows y-1, y, y+1, stored by the output lanes.
+template <bool XEDGE, class V>
+__device__ __forceinline__ void row_second(const KTConsts& K, const V& fo, const Lane2& L, int y,
+                                           const double prev[9], const double cur[9], const double nxt[9]) {
+  double xm[9], xp[9], out[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    xm[i] = shr1(cur[i], cur[i]);
+    xp[i] = shl1(cur[i], cur[i]);
+  }
+  if (XEDGE && !L.perx) {   // ghost_x reads no memory for non-periodic edges
+    if (L.x == 0) ghost_x<0>(K, fo, y, cur, xm);
+    if (L.x == K.nx - 1) ghost_x<1>(K, fo, y, cur, xp);
+  }
+  site_update(K, cur, xp, xm, nxt, prev, out);
+  if (L.out) fo.store9(y, L.vbo, out);
+}
+
+// y ghost row of f1 on edge E (2: below row 0, 3: above row ny-1) for a
+// non-periodic edge, from the f1 row next to it (as ghost_row forms it from the
+// stored f1 at the second step's time). x is the grid column the lane holds.
+template <int E>
+__device__ __forceinline__ void ghost_row_f1(const KTConsts& K, int x, int ish, const double src[9], double r[9]) {
+  const int kind = K.kind[E];
+  if (kind == BC_OUTFLOW) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = src[i];
+  } else if (kind == BC_WALL) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = src[mirror_y(i)];
+  } else {
+    const bool a = (kind == BC_INFLOW) || (x < ish);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = a ? K.ga[E][i] : K.gb[E][i];
+  }
+  if (x < K.split[E]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = K.ga[E][i];
+  }
+}
+
+// f1 of row q of a y-periodic grid, loaded and computed on its own (the far
+// neighbour row of the bottom and top tiles).
+template <bool XEDGE, class V>
+__device__ __forceinline__ void f1_row_periodic(const KTConsts& K, const V& fi, const Lane2& L, int q, double t[9]) {
+  const int ny = K.ny;
+  double pd[9], cd[9], nd[9];
+  Sto<V> h[9];
+  fi.load9_any(q == 0 ? ny - 1 : q - 1, L.vbx, pd);
+  fi.load9_any(q, L.vbx, cd);
+  fi.load9_any(q == ny - 1 ? 0 : q + 1, L.vbx, nd);
+  double hd[9];
+  fi.load9_any(q, L.vbh, hd);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) h[i] = (Sto<V>)hd[i];
+  row_first<XEDGE>(K, fi, L, q, pd, cd, nd, h, t);
+}
+
+// One row of the two-step march: issue the fetches of f0 row y+2 (F) and of the
+// halo of row y+1 (HN), compute f1 of row y, then the second step of row y-1
+// from f1 rows y-2, y-1 (q0, q1) and y; shift the windows.
+template <bool XEDGE, class V>
+__device__ __forceinline__ void march2_row(const KTConsts& K, const V& fi, const V& fo, const Lane2& L, int y,
+                                           int yb, int ylast, double pd[9], double cd[9], double q0[9],
+                                           double q1[9], const Sto<V> N[9], const Sto<V> HC[9], Sto<V> F[9],
+                                           Sto<V> HN[9]) {
+  fi.raw9(min(y + 2, ylast), L.vbx, F);
+  fi.raw9(min(y + 1, yb), L.vbh, HN);
+  double nd[9], t[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) nd[i] = widen(N[i]);
+  row_first<XEDGE>(K, fi, L, y, pd, cd, nd, HC, t);
+  __builtin_amdgcn_sched_barrier(0);   // the two updates one after the other (register pressure)
+  row_second<XEDGE>(K, fo, L, y - 1, q0, q1, t);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    pd[i] = cd[i];
+    cd[i] = nd[i];
+    q0[i] = q1[i];
+    q1[i] = t[i];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// March a 62-column output strip over output rows [y0, y1) (two steps; ny >= 2).
+// f1 rows ya .. yb are computed in order, from f0 rows ya-1 .. min(yb+1, ny-1)
+// fetched as in the one-step march (ghost rows at the first step's time outside
+// the grid); after f1 row y the second step of row y-1 follows. Rows ya and
+// ya+1 prime the f1 window (yb >= ya+1 always holds), after which the register
+// sets are in the same state for every tile.
+template <bool XEDGE, class V>
+__device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& fo, const Lane2& L, int y0, int y1,
+                                       int ish_lo, int ish_hi, int ish2_lo, int ish2_hi) {
+  using S = Sto<V>;
+  const int ny = K.ny;
+  const bool pery = (K.kind[2] == BC_PERIODIC);
+  const int ya = max(y0 - 1, 0), yb = min(y1, ny - 1);
+  const int ylast = min(yb + 1, ny - 1);
+  double pd[9], cd[9], nd[9], q0[9], q1[9];
+  S N0[9], N1[9], H0[9], H1[9];
+  if (ya > 0)
+    fi.load9(ya - 1, L.vbx, pd);
+  else
+    ghost_row<2>(K, fi, L.xs, L.vbx, ish_lo, pd);
+  fi.load9(ya, L.vbx, cd);
+  fi.raw9(ya, L.vbh, H0);
+  fi.raw9(ya + 1, L.vbx, N0);
+  // f1 row ya (its upper f0 neighbour ya+1 <= yb lies in the grid)
+  fi.raw9(min(ya + 2, ylast), L.vbx, N1);
+  fi.raw9(ya + 1, L.vbh, H1);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) nd[i] = widen(N0[i]);
+  row_first<XEDGE>(K, fi, L, ya, pd, cd, nd, H0, q0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    pd[i] = cd[i];
+    cd[i] = nd[i];
+  }
+  // f1 row ya+1 (upper f0 neighbour: the top ghost when ya+1 = ny-1)
+  fi.raw9(min(ya + 3, ylast), L.vbx, N0);
+  fi.raw9(min(ya + 2, yb), L.vbh, H0);
+  if (ya + 1 < ny - 1) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) nd[i] = widen(N1[i]);
+  } else {
+    ghost_row<3>(K, fi, L.xs, L.vbx, ish_hi, nd);
+  }
+  row_first<XEDGE>(K, fi, L, ya + 1, pd, cd, nd, H1, q1);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    pd[i] = cd[i];
+    cd[i] = nd[i];
+  }
+  if (y0 == 0) {   // second step of row 0: f1 rows -1 (ghost), 0, 1
+    double g[9];
+    if (pery)
+      f1_row_periodic<XEDGE>(K, fi, L, ny - 1, g);
+    else
+      ghost_row_f1<2>(K, L.xs, ish2_lo, q0, g);
+    row_second<XEDGE>(K, fo, L, 0, g, q0, q1);
+  }
+  // f1 rows y-2, y-1 in q0, q1; f0 rows y-1, y in pd, cd; in flight: f0 row
+  // min(y+1, ylast) in N0 and the halo of row min(y, yb) in H0
+  int y = ya + 2;
+  for (; y + 1 < ylast; y += 2) {
+    march2_row<XEDGE>(K, fi, fo, L, y, yb, ylast, pd, cd, q0, q1, N0, H0, N1, H1);
+    march2_row<XEDGE>(K, fi, fo, L, y + 1, yb, ylast, pd, cd, q0, q1, N1, H1, N0, H0);
+  }
+  double t[9];
+  if (y < ylast) {
+    march2_row<XEDGE>(K, fi, fo, L, y, yb, ylast, pd, cd, q0, q1, N0, H0, N1, H1);
+    y += 1;
+    if (y <= yb) {   // y = ny-1: the upper f0 neighbour is the top ghost
+      ghost_row<3>(K, fi, L.xs, L.vbx, ish_hi, nd);
+      row_first<XEDGE>(K, fi, L, y, pd, cd, nd, H1, t);
+      row_second<XEDGE>(K, fo, L, y - 1, q0, q1, t);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        q0[i] = q1[i];
+        q1[i] = t[i];
+      }
+    }
+  } else if (y <= yb) {   // y = ny-1
+    ghost_row<3>(K, fi, L.xs, L.vbx, ish_hi, nd);
+    row_first<XEDGE>(K, fi, L, y, pd, cd, nd, H0, t);
+    row_second<XEDGE>(K, fo, L, y - 1, q0, q1, t);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      q0[i] = q1[i];
+      q1[i] = t[i];
+    }
+  }
+  if (y1 == ny) {   // second step of row ny-1: f1 rows ny-2, ny-1, ny (ghost)
+    double g[9];
+    if (pery)
+      f1_row_periodic<XEDGE>(K, fi, L, 0, g);
+    else
+      ghost_row_f1<3>(K, L.xs, ish2_hi, q1, g);
+    row_second<XEDGE>(K, fo, L, ny - 1, q0, q1, g);
+  }
+}
+
+template <typename S, bool WIDE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_step2(KTConsts K, const S* __restrict__ fin, S* __restrict__ fout,
+                                               int rows, int nstrips, int ntiles, int xcd_map, int ish_lo,
+                                               int ish_hi, int ish2_lo, int ish2_hi) {
+  const View<S> fi0 = make_view<S>(K, fin), fo0 = make_view<S>(K, fout);
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  for (int id = blockIdx.x; id < ntiles; id += gridDim.x) {
+    int strip, chunk;
+    tile_of_block(id, nstrips, ntiles, xcd_map, &strip, &chunk);
+    const int X0 = (strip * wpb + (threadIdx.x >> 6)) * 62;
+    if (X0 >= K.nx) continue;   // whole wavefront beyond the grid
+    const int y0 = chunk * rows;
+    const int y1 = min(y0 + rows, K.ny);
+    const Lane2 L = make_lane2<S>(K, X0, lane);
+    // the lanes hold columns X0-1 .. X0+62: x-edge logic when 0 or nx-1 is among them
+    const bool edge = (X0 == 0) || (X0 + 63 >= K.nx);
+    if constexpr (WIDE) {
+      const ViewG<S> fi = make_view_g_rows<S>(K, fin, y0 - 2, y1 + 1);
+      const ViewG<S> fo = make_view_g_rows<S>(K, fout, y0, y1 - 1);
+      if (edge)
+        march2<true>(K, fi, fo, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
+      else
+        march2<false>(K, fi, fo, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
+    } else {
+      if (edge)
+        march2<true>(K, fi0, fo0, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
+      else
+        march2<false>(K, fi0, fo0, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
     }
   }
 }
@@ -1026,6 +1319,7 @@ static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 
 struct Tile {
   int bx, rows, blocks;
+  int steps;   // time steps per pass of lb_run: 1, or 2 (the two-step kernel)
 };
 
 // Default launch shape: 256 x 16 tiles on large grids; on smaller grids the
@@ -1051,9 +1345,13 @@ static lb_status resolve_tile(const lb_tile* tile, int nx, int ny, Tile* t) {
   if (b != 64 && b != 128 && b != 256) return fail(LB_EINVAL, "tile block_x must be 64, 128 or 256");
   if (r < 1) return fail(LB_EINVAL, "tile rows must be >= 1");
   if (nb < 0) return fail(LB_EINVAL, "tile blocks must be >= 0");
+  const int sp = tile ? tile->steps : 0;
+  if (sp < 0 || sp > 2) return fail(LB_EINVAL, "tile steps must be 0, 1 or 2");
   t->bx = b;
   t->rows = std::min(r, ny);
   t->blocks = nb;
+  // two steps per pass need two rows (the f1 window is primed with two rows)
+  t->steps = (ny < 2) ? 1 : (sp == 0 ? 2 : sp);
   return LB_OK;
 }
 
@@ -1080,6 +1378,55 @@ static lb_status launch_step(const lb_grid* g, const KTConsts& K, lb_prec prec, 
                        ntiles, xcd_map, ish_lo, ish_hi);
   }
   HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
+// Two steps f_out = S(S(f_in)) at time indices step, step+1 in one pass.
+static lb_status launch_step2(const lb_grid* g, const KTConsts& K, lb_prec prec, const void* fin, void* fout,
+                              int64_t step, const Tile& t, hipStream_t st) {
+  const bool w = wide(g, elem_size(prec));
+  const int bx = t.bx;
+  const int rows = w ? std::min(t.rows, std::max(1, wide_max_rows(g, elem_size(prec)) - 2)) : t.rows;
+  const int wpb = bx / 64;
+  const int nwaves = (g->nx + 61) / 62;   // 62 output columns per wavefront
+  const int nstrips = (nwaves + wpb - 1) / wpb;
+  const int nchunks = (g->ny + rows - 1) / rows;
+  const int64_t ntiles64 = (int64_t)nstrips * nchunks;
+  if (ntiles64 > 0x7fffffff) return fail(LB_EINVAL, "grid too large for one launch");
+  const int ntiles = (int)ntiles64;
+  const int xcd_map = (ntiles % 8 == 0) ? 1 : 0;
+  int nblocks = ntiles;
+  if (t.blocks > 0 && t.blocks < ntiles) nblocks = xcd_map ? std::max(8, t.blocks & ~7) : t.blocks;
+  const int ish_lo = shock_cells(g, 2, step), ish_hi = shock_cells(g, 3, step);
+  const int ish2_lo = shock_cells(g, 2, step + 1), ish2_hi = shock_cells(g, 3, step + 1);
+  if (prec == LB_F64) {
+    auto kern = w ? k_step2<double, true> : k_step2<double, false>;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fin, (double*)fout, rows, nstrips,
+                       ntiles, xcd_map, ish_lo, ish_hi, ish2_lo, ish2_hi);
+  } else {
+    auto kern = w ? k_step2<float, true> : k_step2<float, false>;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(bx), 0, st, K, (const float*)fin, (float*)fout, rows, nstrips,
+                       ntiles, xcd_map, ish_lo, ish_hi, ish2_lo, ish2_hi);
+  }
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
+// nsteps ping-pong steps from fa (result in fa when nsteps is even, else in fb).
+// With two steps per pass, a pass also swaps the buffers once, so the pairs must
+// be an even number: 2p steps in p passes with p even, and the remaining 0..3
+// steps one per launch, first.
+static lb_status launch_steps(const lb_grid* g, const KTConsts& K, lb_prec prec, void* fa, void* fb, int64_t step0,
+                              int nsteps, const Tile& t, hipStream_t st) {
+  const int pairs = (t.steps == 2) ? (nsteps / 2) & ~1 : 0;
+  const int singles = nsteps - 2 * pairs;
+  int64_t n = step0;
+  int k = 0;   // launches so far: the input is fa when k is even
+  lb_status s;
+  for (int j = 0; j < singles; ++j, ++k, ++n)
+    if ((s = launch_step(g, K, prec, (k % 2 == 0) ? fa : fb, (k % 2 == 0) ? fb : fa, n, t, st))) return s;
+  for (int j = 0; j < pairs; ++j, ++k, n += 2)
+    if ((s = launch_step2(g, K, prec, (k % 2 == 0) ? fa : fb, (k % 2 == 0) ? fb : fa, n, t, st))) return s;
   return LB_OK;
 }
 
@@ -1160,15 +1507,9 @@ extern "C" lb_status lb_run(const lb_grid* g, lb_prec prec, void* fa, void* fb, 
   KTConsts K;
   build_consts(g, &K);
   hipStream_t st = (hipStream_t)stream;
-  if (!use_graph || st == nullptr || nsteps == 0) {
-    for (int n = 0; n < nsteps; ++n) {
-      const void* in = (n % 2 == 0) ? fa : fb;
-      void* out = (n % 2 == 0) ? fb : fa;
-      if ((s = launch_step(g, K, prec, in, out, step0 + n, t, st))) return s;
-    }
-    return LB_OK;
-  }
-  const std::string key = run_key(g, prec, fa, fb, step0, nsteps, t.bx, t.rows * 1000003 + t.blocks, stream);
+  if (!use_graph || st == nullptr || nsteps == 0) return launch_steps(g, K, prec, fa, fb, step0, nsteps, t, st);
+  const std::string key =
+      run_key(g, prec, fa, fb, step0, nsteps, t.bx, (t.rows * 1000003 + t.blocks) * 3 + t.steps, stream);
   std::lock_guard<std::mutex> lock(g_graph_mu);
   for (auto& e : g_graphs)
     if (e.key == key) {
@@ -1176,12 +1517,7 @@ extern "C" lb_status lb_run(const lb_grid* g, lb_prec prec, void* fa, void* fb, 
       return LB_OK;
     }
   HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  lb_status ls = LB_OK;
-  for (int n = 0; n < nsteps && ls == LB_OK; ++n) {
-    const void* in = (n % 2 == 0) ? fa : fb;
-    void* out = (n % 2 == 0) ? fb : fa;
-    ls = launch_step(g, K, prec, in, out, step0 + n, t, st);
-  }
+  const lb_status ls = launch_steps(g, K, prec, fa, fb, step0, nsteps, t, st);
   hipGraph_t graph = nullptr;
   hipError_t ce = hipStreamEndCapture(st, &graph);
   if (ls != LB_OK) {
@@ -1564,7 +1900,7 @@ extern "C" lb_status lb_autotune(const lb_grid* g, lb_prec prec, void* fa, void*
   const int rws[6] = {4, 8, 16, 32, 64, 128};
   const int nbs[3] = {0, 1024, 2048};
   float bestv = 1e30f;
-  lb_tile bt = {256, 16, 0};
+  lb_tile bt = {256, 16, 0, 0};
   KTConsts K;
   build_consts(g, &K);
   for (int bi = 0; bi < 3; ++bi)
@@ -1572,7 +1908,7 @@ extern "C" lb_status lb_autotune(const lb_grid* g, lb_prec prec, void* fa, void*
       for (int ni = 0; ni < 3; ++ni) {
         const int bx = bxs[bi], rows = std::min(rws[ri], g->ny);
         if (ri > 0 && rows == std::min(rws[ri - 1], g->ny)) continue;
-        const Tile t = {bx, rows, nbs[ni]};
+        const Tile t = {bx, rows, nbs[ni], 1};
         // warm-up launch, then reps timed launches
         if ((s = launch_step(g, K, prec, fa, fb, 0, t, st))) goto done;
         if (hipEventRecord(e0, st) != hipSuccess) { s = fail(LB_EHIP, "event record"); goto done; }
