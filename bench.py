@@ -6,11 +6,13 @@ One step = one time step of the finite-difference lattice Boltzmann scheme
 update) over the whole grid, through the C ABI. The workload is the
 double-Mach-reflection field on an 8192 x 2048 grid (a 1.2 GB FP64 / 0.6 GB FP32
 array, too large for the 256 MB on-chip cache), timed as a HIP-graph replay of
-K steps with HIP events on the stream that runs the kernels.
+K steps of lb_run with HIP events on the stream that runs the kernels.
 
-Prints ONE JSON line: MLUPS for FP64 storage (value), the same for FP32 storage,
-each against the HBM roofline; the batched-problem speedup; the adjoint /
-forward time ratio; and the CPU oracle timed on a bounded sample.
+Prints ONE JSON line: MLUPS of lb_run for FP64 storage (value: two time steps per
+pass over the array, its default), the same for FP32 storage, and one step per
+launch (the single fused step kernel) for both, each against the HBM roofline
+of its kernel; the batched-problem speedup; the adjoint / forward time ratio;
+and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -25,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_SITE = {"f64": 144, "f32": 72}   # 9 loads + 9 stores of the storage type
+BYTES_PER_SITE = {"f64": 144, "f32": 72}   # 9 loads + 9 stores of the storage type per pass
 
 
 def log(*a):
@@ -41,15 +43,16 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel, prec):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
-    taken from the current kernel source; else None."""
+    """HBM bytes per launch of `kernel` ("k_step" or "k_step2") from a committed
+    rocprofv3 counter summary, if it was taken from the current kernel source;
+    else None."""
     path = os.path.join(ROOT, "profiles", "traffic_step_roofline_grid.txt")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    e = d.get(prec)
+    e = d.get(kernel, {}).get(prec)
     if not e or d.get("source_hash") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
@@ -61,7 +64,9 @@ def fields_to(dev, fields):
     return [torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev) for a in fields]
 
 
-def time_step(prec, steps, warmup, dev):
+def time_step(prec, steps, warmup, dev, per_pass=2):
+    """lb_run on the roofline grid with `per_pass` time steps per launch (steps a
+    multiple of 4, so that a two-step run is all two-step passes)."""
     import torch
     import paper_0706_0405_amd as lb
     from workloads import problems as P
@@ -76,30 +81,36 @@ def time_step(prec, steps, warmup, dev):
         del rho, ux, uy, p
         tile = None
         if warmup > 0:
-            lb.run(g, fa, fb, warmup, prec=prec, tile=tile)
+            lb.run(g, fa, fb, warmup, prec=prec, tile=tile, steps_per_pass=per_pass)
         # capture the K-step graph once (untimed), then time one replay
-        lb.run(g, fa, fb, steps, prec=prec, use_graph=True, tile=tile)
+        lb.run(g, fa, fb, steps, prec=prec, use_graph=True, tile=tile, steps_per_pass=per_pass)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(s)
-        out = lb.run(g, fa, fb, steps, prec=prec, use_graph=True, tile=tile)
+        out = lb.run(g, fa, fb, steps, prec=prec, use_graph=True, tile=tile, steps_per_pass=per_pass)
         e1.record(s)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         _, _, _, _, flags = lb.moments(g, out, prec=prec)
         torch.cuda.synchronize()
     sites = g.nx * g.ny
-    per_launch_ms = ms / steps
+    launches = steps // per_pass
+    per_launch_ms = ms / launches
     mlups = sites * steps / (ms * 1e-3) / 1e6
     achieved = BYTES_PER_SITE[prec] * sites / (per_launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic("k_step", prec)
+    kname = "k_step" if per_pass == 1 else "k_step2"
+    traffic = measured_traffic(kname, prec)
+    # the one-step HBM bound on the update rate: peak / (bytes per site per step)
+    bound_mlups = HBM_PEAK_GBS * 1e9 / BYTES_PER_SITE[prec] / 1e6
     res = {
-        "mlups": mlups, "ms_per_step": per_launch_ms, "grid": [g.nx, g.ny],
+        "mlups": mlups, "ms_per_step": ms / steps, "steps_per_pass": per_pass, "grid": [g.nx, g.ny],
         "flags": [int(v) for v in flags.cpu().tolist()],
+        "mlups_vs_one_step_hbm_bound": mlups / bound_mlups,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_step<%s>" % ("double" if prec == "f64" else "float"),
+                     "kernel": "%s<%s>" % (kname, "double" if prec == "f64" else "float"),
+                     "launch_ms": per_launch_ms,
                      "algorithmic_bytes_per_launch": BYTES_PER_SITE[prec] * sites},
     }
     del fa, fb, out
@@ -408,8 +419,7 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    if args.steps % 2:
-        args.steps += 1   # even step counts keep the result in the first buffer
+    args.steps += (-args.steps) % 4   # all two-step passes (their count even), result in the first buffer
 
     import torch
     import paper_0706_0405_amd as lb
@@ -419,15 +429,18 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda", 0)
 
-    res = {}
+    res, one = {}, {}
     for prec in (("f64", "f32") if args.prec == "both" else (args.prec,)):
-        log("timing", prec, "step on the roofline grid")
-        res[prec] = time_step(prec, args.steps, args.warmup, dev)
+        log("timing", prec, "lb_run on the roofline grid, two steps per pass")
+        res[prec] = time_step(prec, args.steps, args.warmup, dev, per_pass=2)
         log(prec, json.dumps(res[prec]))
+        log("timing", prec, "lb_run on the roofline grid, one step per launch")
+        one[prec] = time_step(prec, args.steps, args.warmup, dev, per_pass=1)
+        log(prec, json.dumps(one[prec]))
     head = "f64" if "f64" in res else "f32"
     log("timing a device copy of the same size")
     copy = copy_bandwidth(dev)
-    for r_ in res.values():
+    for r_ in list(res.values()) + list(one.values()):
         r_["roofline"]["frac_of_device_copy"] = r_["roofline"]["achieved"] / copy["gbs"]
     extras = {}
     if not args.no_extras:
@@ -440,9 +453,9 @@ def main():
             log(json.dumps(extras["adjoint"]))
         except ImportError as e:
             extras["adjoint"] = {"error": str(e)}
-        if "f32" in res:
+        if "f32" in one:
             log("timing one adjoint step on the roofline grid")
-            extras["adjoint_step"] = bench_adjoint_step(dev, res["f32"]["ms_per_step"])
+            extras["adjoint_step"] = bench_adjoint_step(dev, one["f32"]["ms_per_step"])
             log(json.dumps(extras["adjoint_step"]))
         log("timing the von Neumann chooser")
         extras["vn_scan"] = bench_vn(dev)
@@ -460,15 +473,20 @@ def main():
         "value": r["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "double-Mach-reflection field, %dx%d grid, FP64 storage, one FDLB step"
-                               % tuple(r["grid"]), "storage": head},
+        "config": {"workload": "double-Mach-reflection field, %dx%d grid, FP64 storage, FDLB steps through lb_run "
+                               "(two time steps per pass)" % tuple(r["grid"]), "storage": head, "steps_per_pass": 2},
         "roofline": r["roofline"],
+        "mlups_vs_one_step_hbm_bound": r["mlups_vs_one_step_hbm_bound"],
+        "one_step_per_launch": {p: {"value": one[p]["mlups"], "unit": "MLUPS", "ms_per_step": one[p]["ms_per_step"],
+                                    "roofline": one[p]["roofline"]} for p in one},
         "cpu_baseline": cpu,
         "device_copy": copy,
     }
     if "f32" in res and head != "f32":
         line["fp32_storage"] = {"value": res["f32"]["mlups"], "unit": "MLUPS", "ms_per_step": res["f32"]["ms_per_step"],
-                                "dtype": "f64 arithmetic, f32 storage", "roofline": res["f32"]["roofline"]}
+                                "dtype": "f64 arithmetic, f32 storage", "steps_per_pass": 2,
+                                "mlups_vs_one_step_hbm_bound": res["f32"]["mlups_vs_one_step_hbm_bound"],
+                                "roofline": res["f32"]["roofline"]}
     line.update(extras)
     print(json.dumps(line), flush=True)
 

@@ -666,22 +666,21 @@ __global__ __launch_bounds__(256) LB_STEP_ATTR void k_step(KTConsts K, const S* 
 // forms it from the stored f1, so the result is bitwise that of two single
 // steps.
 //
-// Columns: lane j of a wavefront holds column c = X0 - 1 + j; lanes 1..62 (of
-// columns inside the grid) produce the second step, lanes 0 and 63 hold the f1
-// that those lanes' x-neighbours need, so wavefronts start every 62 columns and
-// overlap by two. With a periodic x axis a lane's column wraps into the grid
-// (lane c = -1 holds column nx-1, so f1 there is the wrapped neighbour itself);
-// otherwise the x ghosts of both steps are formed at columns 0 and nx-1 as in
-// the one-step march. Rows: the tile of output rows [y0, y1) computes f1 on rows
-// y0-1 .. y1 (one extra row each side) from f0 rows y0-2 .. y1+1; the y ghosts
-// of f1 outside the grid come from f1 rows 0 / ny-1 (outflow, wall), from
-// constants at the second step's time (inflow, shock), or for a periodic y axis
-// from f1 computed on the far row.
+// Columns: lane j of a wavefront holds column c = X0 - 2 + j. Lanes 1..62 compute
+// f1 (their x-neighbours are lanes), lanes 2..61 (of columns inside the grid)
+// the second step, so wavefronts start every 60 columns and overlap by four;
+// lanes 0 and 63 only supply f0 to their neighbours, and no halo columns are
+// fetched. With a periodic x axis a lane's column wraps into the grid (lane c =
+// -1 holds column nx-1, the wrapped neighbour itself); otherwise the x ghosts of
+// both steps are formed at columns 0 and nx-1 as in the one-step march. Rows:
+// the tile of output rows [y0, y1) computes f1 on rows y0-1 .. y1 (one extra row
+// each side) from f0 rows y0-2 .. y1+1; the y ghosts of f1 outside the grid come
+// from f1 rows 0 / ny-1 (outflow, wall), from constants at the second step's
+// time (inflow, shock), or for a periodic y axis from f1 computed on the far row.
 struct Lane2 {
-  int x;           // column c (may be -1 or >= nx: then only an x-neighbour)
+  int x;           // column c (may lie outside the grid: then only a neighbour)
   int xs;          // the grid column whose values the lane holds (c wrapped or clamped)
-  uint32_t vbx;    // source column (wrapped or clamped into the grid) * sizeof(S)
-  uint32_t vbh;    // halo source column of lanes 0 / 63 * sizeof(S)
+  uint32_t vbx;    // xs * sizeof(S)
   uint32_t vbo;    // c * sizeof(S) for the output lanes
   bool out;        // lane produces the second step of its column
   bool perx;
@@ -696,29 +695,27 @@ __device__ __forceinline__ Lane2 make_lane2(const KTConsts& K, int X0, int lane)
   Lane2 L;
   const int nx = K.nx;
   L.perx = (K.kind[0] == BC_PERIODIC);
-  L.x = X0 - 1 + lane;
+  L.x = X0 - 2 + lane;
   L.xs = wrap_col(L.x, nx, L.perx);
   L.vbx = (uint32_t)L.xs * sizeof(S);
-  L.vbh = (uint32_t)wrap_col(lane == 0 ? L.x - 1 : L.x + 1, nx, L.perx) * sizeof(S);
-  L.out = (lane >= 1) && (lane <= 62) && (L.x < nx);
+  L.out = (lane >= 2) && (lane <= 61) && (L.x < nx);
   L.vbo = L.out ? (uint32_t)L.x * sizeof(S) : 0u;
   return L;
 }
 
-// f1 of row y at the lane's column from f0 rows y-1, y, y+1 (prev, cur, nxt; hc
-// the halo values of row y), rounded to the storage type.
+// f1 of row y at the lane's column from f0 rows y-1, y, y+1 (prev, cur, nxt),
+// rounded to the storage type (lanes 0 and 63: not meaningful, never used).
 template <bool XEDGE, class V>
 __device__ __forceinline__ void row_first(const KTConsts& K, const V& fi, const Lane2& L, int y,
                                           const double prev[9], const double cur[9], const double nxt[9],
-                                          const Sto<V> hc[9], double t[9]) {
+                                          double t[9]) {
   double xm[9], xp[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const double h = widen(hc[i]);
-    xm[i] = shr1(h, cur[i]);
-    xp[i] = shl1(h, cur[i]);
+    xm[i] = shr1(cur[i], cur[i]);
+    xp[i] = shl1(cur[i], cur[i]);
   }
-  if (XEDGE && !L.perx) {
+  if (XEDGE && !L.perx) {   // ghost_x reads no memory for non-periodic edges
     if (L.x == 0) ghost_x<0>(K, fi, y, cur, xm);
     if (L.x == K.nx - 1) ghost_x<1>(K, fi, y, cur, xp);
   }
@@ -727,17 +724,22 @@ __device__ __forceinline__ void row_first(const KTConsts& K, const V& fi, const 
   for (int i = 0; i < 9; ++i) t[i] = (double)(Sto<V>)t[i];
 }
 
-// The second step of row y from f1 rows y-1, y, y+1, stored by the output lanes.
-template <bool XEDGE, class V>
-__device__ __forceinline__ void row_second(const KTConsts& K, const V& fo, const Lane2& L, int y,
-                                           const double prev[9], const double cur[9], const double nxt[9]) {
-  double xm[9], xp[9], out[9];
+// The second step of row y from f1 rows y-1, y, y+1 (held in the storage type,
+// or in double where a ghost row holds unrounded constants), stored by the
+// output lanes.
+template <bool XEDGE, class V, typename A, typename B, typename C>
+__device__ __forceinline__ void row_second(const KTConsts& K, const V& fo, const Lane2& L, int y, const A p1[9],
+                                           const B c1[9], const C n1[9]) {
+  double prev[9], cur[9], nxt[9], xm[9], xp[9], out[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
+  for (int i = 0; i < 9; ++i) {   // values in registers: plain (exact) conversions
+    prev[i] = (double)p1[i];
+    cur[i] = (double)c1[i];
+    nxt[i] = (double)n1[i];
     xm[i] = shr1(cur[i], cur[i]);
     xp[i] = shl1(cur[i], cur[i]);
   }
-  if (XEDGE && !L.perx) {   // ghost_x reads no memory for non-periodic edges
+  if (XEDGE && !L.perx) {
     if (L.x == 0) ghost_x<0>(K, fo, y, cur, xm);
     if (L.x == K.nx - 1) ghost_x<1>(K, fo, y, cur, xp);
   }
@@ -748,15 +750,15 @@ __device__ __forceinline__ void row_second(const KTConsts& K, const V& fo, const
 // y ghost row of f1 on edge E (2: below row 0, 3: above row ny-1) for a
 // non-periodic edge, from the f1 row next to it (as ghost_row forms it from the
 // stored f1 at the second step's time). x is the grid column the lane holds.
-template <int E>
-__device__ __forceinline__ void ghost_row_f1(const KTConsts& K, int x, int ish, const double src[9], double r[9]) {
+template <int E, typename Q>
+__device__ __forceinline__ void ghost_row_f1(const KTConsts& K, int x, int ish, const Q src[9], double r[9]) {
   const int kind = K.kind[E];
   if (kind == BC_OUTFLOW) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) r[i] = src[i];
+    for (int i = 0; i < 9; ++i) r[i] = (double)src[i];
   } else if (kind == BC_WALL) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) r[i] = src[mirror_y(i)];
+    for (int i = 0; i < 9; ++i) r[i] = (double)src[mirror_y(i)];
   } else {
     const bool a = (kind == BC_INFLOW) || (x < ish);
 #pragma unroll
@@ -774,31 +776,24 @@ template <bool XEDGE, class V>
 __device__ __forceinline__ void f1_row_periodic(const KTConsts& K, const V& fi, const Lane2& L, int q, double t[9]) {
   const int ny = K.ny;
   double pd[9], cd[9], nd[9];
-  Sto<V> h[9];
   fi.load9_any(q == 0 ? ny - 1 : q - 1, L.vbx, pd);
   fi.load9_any(q, L.vbx, cd);
   fi.load9_any(q == ny - 1 ? 0 : q + 1, L.vbx, nd);
-  double hd[9];
-  fi.load9_any(q, L.vbh, hd);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) h[i] = (Sto<V>)hd[i];
-  row_first<XEDGE>(K, fi, L, q, pd, cd, nd, h, t);
+  row_first<XEDGE>(K, fi, L, q, pd, cd, nd, t);
 }
 
-// One row of the two-step march: issue the fetches of f0 row y+2 (F) and of the
-// halo of row y+1 (HN), compute f1 of row y, then the second step of row y-1
-// from f1 rows y-2, y-1 (q0, q1) and y; shift the windows.
+// One row of the two-step march: issue the fetch of f0 row y+2 (F), compute f1
+// of row y, then the second step of row y-1 from f1 rows y-2, y-1 (q0, q1) and
+// y; shift the windows.
 template <bool XEDGE, class V>
 __device__ __forceinline__ void march2_row(const KTConsts& K, const V& fi, const V& fo, const Lane2& L, int y,
-                                           int yb, int ylast, double pd[9], double cd[9], double q0[9],
-                                           double q1[9], const Sto<V> N[9], const Sto<V> HC[9], Sto<V> F[9],
-                                           Sto<V> HN[9]) {
+                                           int ylast, double pd[9], double cd[9], Sto<V> q0[9], Sto<V> q1[9],
+                                           const Sto<V> N[9], Sto<V> F[9]) {
   fi.raw9(min(y + 2, ylast), L.vbx, F);
-  fi.raw9(min(y + 1, yb), L.vbh, HN);
   double nd[9], t[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) nd[i] = widen(N[i]);
-  row_first<XEDGE>(K, fi, L, y, pd, cd, nd, HC, t);
+  row_first<XEDGE>(K, fi, L, y, pd, cd, nd, t);
   __builtin_amdgcn_sched_barrier(0);   // the two updates one after the other (register pressure)
   row_second<XEDGE>(K, fo, L, y - 1, q0, q1, t);
 #pragma unroll
@@ -806,12 +801,12 @@ __device__ __forceinline__ void march2_row(const KTConsts& K, const V& fi, const
     pd[i] = cd[i];
     cd[i] = nd[i];
     q0[i] = q1[i];
-    q1[i] = t[i];
+    q1[i] = (Sto<V>)t[i];   // exact: t is already rounded to the storage type
   }
   __builtin_amdgcn_sched_barrier(0);
 }
 
-// March a 62-column output strip over output rows [y0, y1) (two steps; ny >= 2).
+// March a 60-column output strip over output rows [y0, y1) (two steps; ny >= 2).
 // f1 rows ya .. yb are computed in order, from f0 rows ya-1 .. min(yb+1, ny-1)
 // fetched as in the one-step march (ghost rows at the first step's time outside
 // the grid); after f1 row y the second step of row y-1 follows. Rows ya and
@@ -825,38 +820,37 @@ __device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& 
   const bool pery = (K.kind[2] == BC_PERIODIC);
   const int ya = max(y0 - 1, 0), yb = min(y1, ny - 1);
   const int ylast = min(yb + 1, ny - 1);
-  double pd[9], cd[9], nd[9], q0[9], q1[9];
-  S N0[9], N1[9], H0[9], H1[9];
+  double pd[9], cd[9], nd[9], t[9];
+  S N0[9], N1[9], q0[9], q1[9];   // q0, q1: f1 rows y-2, y-1
   if (ya > 0)
     fi.load9(ya - 1, L.vbx, pd);
   else
     ghost_row<2>(K, fi, L.xs, L.vbx, ish_lo, pd);
   fi.load9(ya, L.vbx, cd);
-  fi.raw9(ya, L.vbh, H0);
   fi.raw9(ya + 1, L.vbx, N0);
   // f1 row ya (its upper f0 neighbour ya+1 <= yb lies in the grid)
   fi.raw9(min(ya + 2, ylast), L.vbx, N1);
-  fi.raw9(ya + 1, L.vbh, H1);
 #pragma unroll
   for (int i = 0; i < 9; ++i) nd[i] = widen(N0[i]);
-  row_first<XEDGE>(K, fi, L, ya, pd, cd, nd, H0, q0);
+  row_first<XEDGE>(K, fi, L, ya, pd, cd, nd, t);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
+    q0[i] = (S)t[i];
     pd[i] = cd[i];
     cd[i] = nd[i];
   }
   // f1 row ya+1 (upper f0 neighbour: the top ghost when ya+1 = ny-1)
   fi.raw9(min(ya + 3, ylast), L.vbx, N0);
-  fi.raw9(min(ya + 2, yb), L.vbh, H0);
   if (ya + 1 < ny - 1) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) nd[i] = widen(N1[i]);
   } else {
     ghost_row<3>(K, fi, L.xs, L.vbx, ish_hi, nd);
   }
-  row_first<XEDGE>(K, fi, L, ya + 1, pd, cd, nd, H1, q1);
+  row_first<XEDGE>(K, fi, L, ya + 1, pd, cd, nd, t);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
+    q1[i] = (S)t[i];
     pd[i] = cd[i];
     cd[i] = nd[i];
   }
@@ -869,34 +863,24 @@ __device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& 
     row_second<XEDGE>(K, fo, L, 0, g, q0, q1);
   }
   // f1 rows y-2, y-1 in q0, q1; f0 rows y-1, y in pd, cd; in flight: f0 row
-  // min(y+1, ylast) in N0 and the halo of row min(y, yb) in H0
+  // min(y+1, ylast) in N0
   int y = ya + 2;
   for (; y + 1 < ylast; y += 2) {
-    march2_row<XEDGE>(K, fi, fo, L, y, yb, ylast, pd, cd, q0, q1, N0, H0, N1, H1);
-    march2_row<XEDGE>(K, fi, fo, L, y + 1, yb, ylast, pd, cd, q0, q1, N1, H1, N0, H0);
+    march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N0, N1);
+    march2_row<XEDGE>(K, fi, fo, L, y + 1, ylast, pd, cd, q0, q1, N1, N0);
   }
-  double t[9];
   if (y < ylast) {
-    march2_row<XEDGE>(K, fi, fo, L, y, yb, ylast, pd, cd, q0, q1, N0, H0, N1, H1);
+    march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N0, N1);
     y += 1;
-    if (y <= yb) {   // y = ny-1: the upper f0 neighbour is the top ghost
-      ghost_row<3>(K, fi, L.xs, L.vbx, ish_hi, nd);
-      row_first<XEDGE>(K, fi, L, y, pd, cd, nd, H1, t);
-      row_second<XEDGE>(K, fo, L, y - 1, q0, q1, t);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        q0[i] = q1[i];
-        q1[i] = t[i];
-      }
-    }
-  } else if (y <= yb) {   // y = ny-1
+  }
+  if (y <= yb) {   // y = ny-1: the upper f0 neighbour is the top ghost
     ghost_row<3>(K, fi, L.xs, L.vbx, ish_hi, nd);
-    row_first<XEDGE>(K, fi, L, y, pd, cd, nd, H0, t);
+    row_first<XEDGE>(K, fi, L, y, pd, cd, nd, t);
     row_second<XEDGE>(K, fo, L, y - 1, q0, q1, t);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       q0[i] = q1[i];
-      q1[i] = t[i];
+      q1[i] = (S)t[i];
     }
   }
   if (y1 == ny) {   // second step of row ny-1: f1 rows ny-2, ny-1, ny (ghost)
@@ -910,22 +894,22 @@ __device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& 
 }
 
 template <typename S, bool WIDE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_step2(KTConsts K, const S* __restrict__ fin, S* __restrict__ fout,
-                                               int rows, int nstrips, int ntiles, int xcd_map, int ish_lo,
-                                               int ish_hi, int ish2_lo, int ish2_hi) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_step2(
+    KTConsts K, const S* __restrict__ fin, S* __restrict__ fout, int rows, int nstrips, int ntiles, int xcd_map,
+    int ish_lo, int ish_hi, int ish2_lo, int ish2_hi) {
   const View<S> fi0 = make_view<S>(K, fin), fo0 = make_view<S>(K, fout);
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
   for (int id = blockIdx.x; id < ntiles; id += gridDim.x) {
     int strip, chunk;
     tile_of_block(id, nstrips, ntiles, xcd_map, &strip, &chunk);
-    const int X0 = (strip * wpb + (threadIdx.x >> 6)) * 62;
+    const int X0 = (strip * wpb + (threadIdx.x >> 6)) * 60;
     if (X0 >= K.nx) continue;   // whole wavefront beyond the grid
     const int y0 = chunk * rows;
     const int y1 = min(y0 + rows, K.ny);
     const Lane2 L = make_lane2<S>(K, X0, lane);
-    // the lanes hold columns X0-1 .. X0+62: x-edge logic when 0 or nx-1 is among them
-    const bool edge = (X0 == 0) || (X0 + 63 >= K.nx);
+    // the lanes hold columns X0-2 .. X0+61: x-edge logic when 0 or nx-1 is among them
+    const bool edge = (X0 == 0) || (X0 + 62 >= K.nx);
     if constexpr (WIDE) {
       const ViewG<S> fi = make_view_g_rows<S>(K, fin, y0 - 2, y1 + 1);
       const ViewG<S> fo = make_view_g_rows<S>(K, fout, y0, y1 - 1);
@@ -1320,6 +1304,7 @@ static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 struct Tile {
   int bx, rows, blocks;
   int steps;   // time steps per pass of lb_run: 1, or 2 (the two-step kernel)
+  int rows2;   // tile height of the two-step kernel
 };
 
 // Default launch shape: 256 x 16 tiles on large grids; on smaller grids the
@@ -1337,9 +1322,12 @@ static void default_tile(int nx, int ny, int* bx, int* rows) {
 static lb_status resolve_tile(const lb_tile* tile, int nx, int ny, Tile* t) {
   int b, r, nb = 0;
   default_tile(nx, ny, &b, &r);
+  // the two-step kernel's default is at most 16 rows (measured: 256 x 16 beats
+  // 256 x 32 by 4-5% on the 8192 x 2048 grid, the one-step kernel by < 1%)
+  int r2 = std::min(r, 16);
   if (tile && (tile->block_x || tile->rows || tile->blocks)) {
     b = tile->block_x;
-    r = tile->rows;
+    r = r2 = tile->rows;
     nb = tile->blocks;
   }
   if (b != 64 && b != 128 && b != 256) return fail(LB_EINVAL, "tile block_x must be 64, 128 or 256");
@@ -1349,6 +1337,7 @@ static lb_status resolve_tile(const lb_tile* tile, int nx, int ny, Tile* t) {
   if (sp < 0 || sp > 2) return fail(LB_EINVAL, "tile steps must be 0, 1 or 2");
   t->bx = b;
   t->rows = std::min(r, ny);
+  t->rows2 = std::min(r2, ny);
   t->blocks = nb;
   // two steps per pass need two rows (the f1 window is primed with two rows)
   t->steps = (ny < 2) ? 1 : (sp == 0 ? 2 : sp);
@@ -1386,9 +1375,9 @@ static lb_status launch_step2(const lb_grid* g, const KTConsts& K, lb_prec prec,
                               int64_t step, const Tile& t, hipStream_t st) {
   const bool w = wide(g, elem_size(prec));
   const int bx = t.bx;
-  const int rows = w ? std::min(t.rows, std::max(1, wide_max_rows(g, elem_size(prec)) - 2)) : t.rows;
+  const int rows = w ? std::min(t.rows2, wide_max_rows(g, elem_size(prec)) - 2) : t.rows2;   // >= 1 (launch_steps)
   const int wpb = bx / 64;
-  const int nwaves = (g->nx + 61) / 62;   // 62 output columns per wavefront
+  const int nwaves = (g->nx + 59) / 60;   // 60 output columns per wavefront
   const int nstrips = (nwaves + wpb - 1) / wpb;
   const int nchunks = (g->ny + rows - 1) / rows;
   const int64_t ntiles64 = (int64_t)nstrips * nchunks;
@@ -1418,7 +1407,9 @@ static lb_status launch_step2(const lb_grid* g, const KTConsts& K, lb_prec prec,
 // steps one per launch, first.
 static lb_status launch_steps(const lb_grid* g, const KTConsts& K, lb_prec prec, void* fa, void* fb, int64_t step0,
                               int nsteps, const Tile& t, hipStream_t st) {
-  const int pairs = (t.steps == 2) ? (nsteps / 2) & ~1 : 0;
+  // a large array's two-step window (tile rows + 4 rows) must stay below 4 GiB
+  const bool two = (t.steps == 2) && (!wide(g, elem_size(prec)) || wide_max_rows(g, elem_size(prec)) >= 3);
+  const int pairs = two ? (nsteps / 2) & ~1 : 0;
   const int singles = nsteps - 2 * pairs;
   int64_t n = step0;
   int k = 0;   // launches so far: the input is fa when k is even
@@ -1908,7 +1899,7 @@ extern "C" lb_status lb_autotune(const lb_grid* g, lb_prec prec, void* fa, void*
       for (int ni = 0; ni < 3; ++ni) {
         const int bx = bxs[bi], rows = std::min(rws[ri], g->ny);
         if (ri > 0 && rows == std::min(rws[ri - 1], g->ny)) continue;
-        const Tile t = {bx, rows, nbs[ni], 1};
+        const Tile t = {bx, rows, nbs[ni], 1, rows};
         // warm-up launch, then reps timed launches
         if ((s = launch_step(g, K, prec, fa, fb, 0, t, st))) goto done;
         if (hipEventRecord(e0, st) != hipSuccess) { s = fail(LB_EHIP, "event record"); goto done; }

@@ -50,9 +50,11 @@ def _is_wide(g, nbytes):
     return 9 * g.pitch * g.ny * nbytes >= 1 << 32
 
 
+@pytest.mark.parametrize("spp", [1, 2])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_periodic_repeat_bitwise_equal_to_small_grid(prec):
-    """4 steps, then moments, on a y-periodic 8192-wide grid of 64-row repeats."""
+def test_periodic_repeat_bitwise_equal_to_small_grid(prec, spp):
+    """4 steps (one or two per pass), then moments, on a y-periodic 8192-wide grid of
+    64-row repeats."""
     lb = _lb()
     per = [_edge("periodic") for _ in range(4)]
     small = _grid(lb, 64, per)
@@ -63,9 +65,9 @@ def test_periodic_repeat_bitwise_equal_to_small_grid(prec):
     s0 = _put(lb, small, prec, _block(64, seed=41))
     Fa = lb.empty(big, prec, DEV)
     Fa.view(9, reps, 64, big.pitch)[:] = s0.unsqueeze(1)
-    want = lb.run(small, s0, lb.empty(small, prec, DEV), 4, prec=prec).clone()
+    want = lb.run(small, s0, lb.empty(small, prec, DEV), 4, prec=prec, steps_per_pass=spp).clone()
     Fb = lb.empty(big, prec, DEV)
-    got = lb.run(big, Fa, Fb, 4, prec=prec)
+    got = lb.run(big, Fa, Fb, 4, prec=prec, steps_per_pass=spp)
     same = bool((got.view(9, reps, 64, big.pitch)[..., :NX] == want[:, None, :, :NX]).all())
     say("all elements equal:", same)
     assert same
@@ -103,7 +105,13 @@ def test_edges_one_step_sampled_rows_and_edge_bands(prec):
     say("sampled rows max rel err", err)
     assert err < (1e-13 if prec == "f64" else 1.2e-7)
     lo, hi = out[:, :64, :NX].clone(), out[:, -64:, :NX].clone()
-    del f, out
+    # four steps, two per pass, equal four single steps on the large array
+    a, b = f.clone(), lb.empty(big, prec, DEV)
+    two = lb.run(big, a, b, 4, prec=prec, steps_per_pass=2)
+    c, d = f, out
+    one = lb.run(big, c, d, 4, prec=prec, steps_per_pass=1)
+    assert bool((two[..., :NX] == one[..., :NX]).all())
+    del a, b, c, d, two, one, f, out
     torch.cuda.empty_cache()
     small = _grid(lb, 128, edges)
     for band, part in ((lo, src[:, :128]), (hi, src[:, -128:])):
