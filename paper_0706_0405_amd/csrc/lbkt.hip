@@ -782,14 +782,14 @@ __device__ __forceinline__ void f1_row_periodic(const KTConsts& K, const V& fi, 
   row_first<XEDGE>(K, fi, L, q, pd, cd, nd, t);
 }
 
-// One row of the two-step march: issue the fetch of f0 row y+2 (F), compute f1
-// of row y, then the second step of row y-1 from f1 rows y-2, y-1 (q0, q1) and
-// y; shift the windows.
+// One row of the two-step march: issue the fetch of f0 row y+3 (F), compute f1
+// of row y (N: f0 row y+1, fetched two rows earlier), then the second step of
+// row y-1 from f1 rows y-2, y-1 (q0, q1) and y; shift the windows.
 template <bool XEDGE, class V>
 __device__ __forceinline__ void march2_row(const KTConsts& K, const V& fi, const V& fo, const Lane2& L, int y,
                                            int ylast, double pd[9], double cd[9], Sto<V> q0[9], Sto<V> q1[9],
                                            const Sto<V> N[9], Sto<V> F[9]) {
-  fi.raw9(min(y + 2, ylast), L.vbx, F);
+  fi.raw9(min(y + 3, ylast), L.vbx, F);
   double nd[9], t[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) nd[i] = widen(N[i]);
@@ -821,15 +821,16 @@ __device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& 
   const int ya = max(y0 - 1, 0), yb = min(y1, ny - 1);
   const int ylast = min(yb + 1, ny - 1);
   double pd[9], cd[9], nd[9], t[9];
-  S N0[9], N1[9], q0[9], q1[9];   // q0, q1: f1 rows y-2, y-1
+  S N0[9], N1[9], N2[9], q0[9], q1[9];   // f0 rows in flight (three sets); f1 rows y-2, y-1
   if (ya > 0)
     fi.load9(ya - 1, L.vbx, pd);
   else
     ghost_row<2>(K, fi, L.xs, L.vbx, ish_lo, pd);
   fi.load9(ya, L.vbx, cd);
   fi.raw9(ya + 1, L.vbx, N0);
-  // f1 row ya (its upper f0 neighbour ya+1 <= yb lies in the grid)
   fi.raw9(min(ya + 2, ylast), L.vbx, N1);
+  // f1 row ya (its upper f0 neighbour ya+1 <= yb lies in the grid)
+  fi.raw9(min(ya + 3, ylast), L.vbx, N2);
 #pragma unroll
   for (int i = 0; i < 9; ++i) nd[i] = widen(N0[i]);
   row_first<XEDGE>(K, fi, L, ya, pd, cd, nd, t);
@@ -840,7 +841,7 @@ __device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& 
     cd[i] = nd[i];
   }
   // f1 row ya+1 (upper f0 neighbour: the top ghost when ya+1 = ny-1)
-  fi.raw9(min(ya + 3, ylast), L.vbx, N0);
+  fi.raw9(min(ya + 4, ylast), L.vbx, N0);
   if (ya + 1 < ny - 1) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) nd[i] = widen(N1[i]);
@@ -862,16 +863,22 @@ __device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& 
       ghost_row_f1<2>(K, L.xs, ish2_lo, q0, g);
     row_second<XEDGE>(K, fo, L, 0, g, q0, q1);
   }
-  // f1 rows y-2, y-1 in q0, q1; f0 rows y-1, y in pd, cd; in flight: f0 row
-  // min(y+1, ylast) in N0
+  // f1 rows y-2, y-1 in q0, q1; f0 rows y-1, y in pd, cd; in flight: f0 rows
+  // min(y+1, ylast) in N2 and min(y+2, ylast) in N0; N1 free. The sets rotate
+  // with period three (the loop is unrolled by three).
   int y = ya + 2;
-  for (; y + 1 < ylast; y += 2) {
-    march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N0, N1);
-    march2_row<XEDGE>(K, fi, fo, L, y + 1, ylast, pd, cd, q0, q1, N1, N0);
+  for (; y + 2 < ylast; y += 3) {
+    march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N2, N1);
+    march2_row<XEDGE>(K, fi, fo, L, y + 1, ylast, pd, cd, q0, q1, N0, N2);
+    march2_row<XEDGE>(K, fi, fo, L, y + 2, ylast, pd, cd, q0, q1, N1, N0);
   }
   if (y < ylast) {
-    march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N0, N1);
+    march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N2, N1);
     y += 1;
+    if (y < ylast) {
+      march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N0, N2);
+      y += 1;
+    }
   }
   if (y <= yb) {   // y = ny-1: the upper f0 neighbour is the top ghost
     ghost_row<3>(K, fi, L.xs, L.vbx, ish_hi, nd);
@@ -1304,7 +1311,7 @@ static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 struct Tile {
   int bx, rows, blocks;
   int steps;   // time steps per pass of lb_run: 1, or 2 (the two-step kernel)
-  int rows2;   // tile height of the two-step kernel
+  bool user;   // shape given by the caller (else the default, per kernel)
 };
 
 // Default launch shape: 256 x 16 tiles on large grids; on smaller grids the
@@ -1322,12 +1329,10 @@ static void default_tile(int nx, int ny, int* bx, int* rows) {
 static lb_status resolve_tile(const lb_tile* tile, int nx, int ny, Tile* t) {
   int b, r, nb = 0;
   default_tile(nx, ny, &b, &r);
-  // the two-step kernel's default is at most 16 rows (measured: 256 x 16 beats
-  // 256 x 32 by 4-5% on the 8192 x 2048 grid, the one-step kernel by < 1%)
-  int r2 = std::min(r, 16);
-  if (tile && (tile->block_x || tile->rows || tile->blocks)) {
+  const bool user = tile && (tile->block_x || tile->rows || tile->blocks);
+  if (user) {
     b = tile->block_x;
-    r = r2 = tile->rows;
+    r = tile->rows;
     nb = tile->blocks;
   }
   if (b != 64 && b != 128 && b != 256) return fail(LB_EINVAL, "tile block_x must be 64, 128 or 256");
@@ -1337,8 +1342,8 @@ static lb_status resolve_tile(const lb_tile* tile, int nx, int ny, Tile* t) {
   if (sp < 0 || sp > 2) return fail(LB_EINVAL, "tile steps must be 0, 1 or 2");
   t->bx = b;
   t->rows = std::min(r, ny);
-  t->rows2 = std::min(r2, ny);
   t->blocks = nb;
+  t->user = user;
   // two steps per pass need two rows (the f1 window is primed with two rows)
   t->steps = (ny < 2) ? 1 : (sp == 0 ? 2 : sp);
   return LB_OK;
@@ -1375,7 +1380,10 @@ static lb_status launch_step2(const lb_grid* g, const KTConsts& K, lb_prec prec,
                               int64_t step, const Tile& t, hipStream_t st) {
   const bool w = wide(g, elem_size(prec));
   const int bx = t.bx;
-  const int rows = w ? std::min(t.rows2, wide_max_rows(g, elem_size(prec)) - 2) : t.rows2;   // >= 1 (launch_steps)
+  // default tile height of the two-step kernel: at most 12 rows (double) or 24
+  // (float), the fastest measured on the 8192 x 2048 grid (8..48 tried)
+  int rows = t.user ? t.rows : std::min(t.rows, prec == LB_F64 ? 12 : 24);
+  if (w) rows = std::min(rows, wide_max_rows(g, elem_size(prec)) - 2);   // >= 1 (launch_steps)
   const int wpb = bx / 64;
   const int nwaves = (g->nx + 59) / 60;   // 60 output columns per wavefront
   const int nstrips = (nwaves + wpb - 1) / wpb;
@@ -1899,7 +1907,7 @@ extern "C" lb_status lb_autotune(const lb_grid* g, lb_prec prec, void* fa, void*
       for (int ni = 0; ni < 3; ++ni) {
         const int bx = bxs[bi], rows = std::min(rws[ri], g->ny);
         if (ri > 0 && rows == std::min(rws[ri - 1], g->ny)) continue;
-        const Tile t = {bx, rows, nbs[ni], 1, rows};
+        const Tile t = {bx, rows, nbs[ni], 1, true};
         // warm-up launch, then reps timed launches
         if ((s = launch_step(g, K, prec, fa, fb, 0, t, st))) goto done;
         if (hipEventRecord(e0, st) != hipSuccess) { s = fail(LB_EHIP, "event record"); goto done; }
