@@ -438,6 +438,21 @@ __device__ __forceinline__ double shl1(double old, double v) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// The same shifts where the lane without a source (0, resp. 63) may receive 0:
+// no old value to carry, so no copy of it before the shift.
+__device__ __forceinline__ double shr1z(double v) {
+  const unsigned long long w = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)w, 0x138, 0xF, 0xF, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(w >> 32), 0x138, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double shl1z(double v) {
+  const unsigned long long w = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)w, 0x130, 0xF, 0xF, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(w >> 32), 0x130, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Column geometry of one lane: its column x inside a wavefront that covers the
 // 64 columns [xw0, xw0 + 64); lanes 0 and 63 also fetch the halo columns hl, hr.
 struct Lane {
@@ -712,8 +727,8 @@ __device__ __forceinline__ void row_first(const KTConsts& K, const V& fi, const 
   double xm[9], xp[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    xm[i] = shr1(cur[i], cur[i]);
-    xp[i] = shl1(cur[i], cur[i]);
+    xm[i] = shr1z(cur[i]);   // lanes 0 and 63 get 0: their results are never used
+    xp[i] = shl1z(cur[i]);
   }
   if (XEDGE && !L.perx) {   // ghost_x reads no memory for non-periodic edges
     if (L.x == 0) ghost_x<0>(K, fi, y, cur, xm);
@@ -736,8 +751,8 @@ __device__ __forceinline__ void row_second(const KTConsts& K, const V& fo, const
     prev[i] = (double)p1[i];
     cur[i] = (double)c1[i];
     nxt[i] = (double)n1[i];
-    xm[i] = shr1(cur[i], cur[i]);
-    xp[i] = shl1(cur[i], cur[i]);
+    xm[i] = shr1z(cur[i]);   // lanes 0 and 63 get 0: their results are never used
+    xp[i] = shl1z(cur[i]);
   }
   if (XEDGE && !L.perx) {
     if (L.x == 0) ghost_x<0>(K, fo, y, cur, xm);
