@@ -125,12 +125,14 @@ def init(grid: Grid, rho, ux, uy, p, prec="f64", out=None):
 
 
 def _tile(tile, steps=0):
-    """(block_x, rows[, blocks]) -> lb_tile; None = the library's default shape.
-    steps: time steps per pass of lb_run (0 = default, 1 or 2)."""
+    """(block_x, rows[, blocks[, steps]]) -> lb_tile; None = the library's default shape.
+    steps: time steps per pass of lb_run (0 = the tile's own, else the default; 1 or 2)."""
     if tile is None and not steps:
         return None
     t = tuple(tile) if tile is not None else (0, 0)
     blocks = int(t[2]) if len(t) > 2 else 0
+    if not steps and len(t) > 3:   # a tuned shape carries its steps per pass
+        steps = int(t[3])
     return ctypes.byref(LbTile(int(t[0]), int(t[1]), blocks, int(steps)))
 
 
@@ -228,7 +230,8 @@ def init_adjoint(grid: Grid, rho, ux, uy, p, g_f0):
 
 
 def autotune(grid: Grid, f_a, f_b, prec="f64", reps=10):
-    """Fastest (block_x, rows) for this grid, timed with HIP events (lb_autotune)."""
+    """Fastest (block_x, rows, blocks, steps_per_pass) for lb_run on this grid and its
+    time per step, timed with HIP events (lb_autotune)."""
     pr = _prec(prec)
     _check_f(grid, pr, f_a, "f_a")
     _check_f(grid, pr, f_b, "f_b")
@@ -236,7 +239,7 @@ def autotune(grid: Grid, f_a, f_b, prec="f64", reps=10):
     ms = ctypes.c_float()
     check(lib().lb_autotune(ctypes.byref(grid.c()), pr, _ptr(f_a), _ptr(f_b), int(reps), ctypes.byref(best),
                             ctypes.byref(ms), _stream(f_a.device)))
-    return (best.block_x, best.rows, best.blocks), ms.value
+    return (best.block_x, best.rows, best.blocks, best.steps), ms.value
 
 
 def interior(grid: Grid, f):

@@ -1916,37 +1916,43 @@ extern "C" lb_status lb_autotune(const lb_grid* g, lb_prec prec, void* fa, void*
   HIP_CHECK(hipEventCreate(&e0));
   HIP_CHECK(hipEventCreate(&e1));
   const int bxs[3] = {64, 128, 256};
-  const int rws[6] = {4, 8, 16, 32, 64, 128};
+  const int rws[7] = {4, 8, 12, 16, 24, 32, 64};
   const int nbs[3] = {0, 1024, 2048};
   float bestv = 1e30f;
   lb_tile bt = {256, 16, 0, 0};
   KTConsts K;
   build_consts(g, &K);
-  for (int bi = 0; bi < 3; ++bi)
-    for (int ri = 0; ri < 6; ++ri)
-      for (int ni = 0; ni < 3; ++ni) {
-        const int bx = bxs[bi], rows = std::min(rws[ri], g->ny);
-        if (ri > 0 && rows == std::min(rws[ri - 1], g->ny)) continue;
-        const Tile t = {bx, rows, nbs[ni], 1, true};
-        // warm-up launch, then reps timed launches
-        if ((s = launch_step(g, K, prec, fa, fb, 0, t, st))) goto done;
-        if (hipEventRecord(e0, st) != hipSuccess) { s = fail(LB_EHIP, "event record"); goto done; }
-        for (int n = 0; n < reps; ++n)
-          if ((s = launch_step(g, K, prec, (n % 2 == 0) ? fb : fa, (n % 2 == 0) ? fa : fb, 0, t, st))) goto done;
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-          s = fail(LB_EHIP, "event sync");
-          goto done;
+  // both kernels lb_run can use: one step per launch, and two per pass (ny >= 2)
+  for (int sp = 1; sp <= (g->ny >= 2 ? 2 : 1); ++sp)
+    for (int bi = 0; bi < 3; ++bi)
+      for (int ri = 0; ri < 7; ++ri)
+        for (int ni = 0; ni < 3; ++ni) {
+          const int bx = bxs[bi], rows = std::min(rws[ri], g->ny);
+          if (ri > 0 && rows == std::min(rws[ri - 1], g->ny)) continue;
+          const Tile t = {bx, rows, nbs[ni], sp, true};
+          auto launch = [&](const void* in, void* out) {
+            return sp == 1 ? launch_step(g, K, prec, in, out, 0, t, st) : launch_step2(g, K, prec, in, out, 0, t, st);
+          };
+          // warm-up launch, then reps timed launches
+          if ((s = launch(fa, fb))) goto done;
+          if (hipEventRecord(e0, st) != hipSuccess) { s = fail(LB_EHIP, "event record"); goto done; }
+          for (int n = 0; n < reps; ++n)
+            if ((s = launch((n % 2 == 0) ? fb : fa, (n % 2 == 0) ? fa : fb))) goto done;
+          if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            s = fail(LB_EHIP, "event sync");
+            goto done;
+          }
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          ms /= (float)(reps * sp);   // per time step
+          if (ms < bestv) {
+            bestv = ms;
+            bt.block_x = bx;
+            bt.rows = rows;
+            bt.blocks = nbs[ni];
+            bt.steps = sp;
+          }
         }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        ms /= reps;
-        if (ms < bestv) {
-          bestv = ms;
-          bt.block_x = bx;
-          bt.rows = rows;
-          bt.blocks = nbs[ni];
-        }
-      }
 done:
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

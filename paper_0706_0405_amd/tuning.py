@@ -1,7 +1,7 @@
 """Launch-shape autotuner with an on-disk cache.
 
-Single grid: lb_autotune times every (block_x, rows) candidate with HIP events
-on the real grid. Batched: each block_x candidate of the packed work list is
+Single grid: lb_autotune times every (block_x, rows, blocks) candidate, one step
+per launch and two steps per pass, with HIP events on the real grid. Batched: each block_x candidate of the packed work list is
 timed over a few graph-launched steps. Results are cached in a JSON file keyed
 by device name, precision and shape, so later runs reuse them.
 """
@@ -37,7 +37,8 @@ def _key(kind, prec, shape):
 
 
 def tile_for(grid: api.Grid, f_a, f_b, prec="f64", reps=10, refresh=False):
-    """Best (block_x, rows) for this grid shape; f_a/f_b are overwritten."""
+    """Best (block_x, rows, blocks, steps_per_pass) of lb_run for this grid shape
+    (pass it as lb.run(..., tile=...)); f_a/f_b are overwritten."""
     d = _load()
     k = _key("step", prec, "%dx%d" % (grid.nx, grid.ny))
     if k in d and not refresh:
