@@ -114,6 +114,17 @@ def test_batched_problem_over_4_gib_rejected():
     assert b"4 GiB" in L.lb_last_error() and not out.value
 
 
+def test_tile_steps_validated_before_launch():
+    """lb_tile.steps (time steps per pass of lb_run) must be 0, 1 or 2."""
+    L = _lib.lib()
+    g = _grid().c()
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)   # never dereferenced
+    for steps, want in ((3, -1), (-1, -1)):
+        t = _lib.LbTile(0, 0, 0, steps)
+        st = L.lb_run(ctypes.byref(g), 0, a, b, 0, 4, 0, ctypes.byref(t), None)
+        assert st == want and b"steps" in L.lb_last_error()
+
+
 def test_alias_and_alignment_rejected_before_launch():
     L = _lib.lib()
     g = _grid().c()
