@@ -5,10 +5,12 @@
 // bound by HBM bandwidth (9 loads + 9 stores per site). Each thread owns one
 // column x and marches up a chunk of `rows` rows, keeping the rows y-1, y, y+1
 // of all 9 planes in registers, so every row is read from memory once per
-// chunk; the x-neighbours are re-read from the row just fetched (L1/L2 hits).
-// Boundary ghosts are synthesised in registers. All kernels share one per-site
-// arithmetic routine (kt_site.hpp), so every launch shape and the batched path
-// give bitwise identical results.
+// chunk; the x-neighbours come from the adjacent lanes (DPP shifts), the
+// wavefront's two edge columns from halo fetches. The two-step pass (k_step2)
+// applies two steps per pass over the array with the intermediate state in
+// registers. Boundary ghosts are synthesised in registers. All kernels share
+// one per-site arithmetic routine (kt_site.hpp), so every launch shape, one or
+// two steps per pass and the batched path give bitwise identical results.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
