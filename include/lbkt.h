@@ -218,13 +218,16 @@ lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, lb_prec prec, lb_
 lb_status lb_batch_layout(const lb_batch* b, int64_t* offsets, int64_t* pitches, int64_t* total);
 
 /* Set the launch shape of the batched step (block_x threads per work item;
- * rows is ignored: a work item covers all rows of its problem). */
+ * rows and blocks are ignored: a work item covers all rows of its problem;
+ * steps: time steps per pass, 0 = the default, 1 or 2). */
 lb_status lb_batch_set_tile(lb_batch* b, const lb_tile* tile);
 
-/* nsteps steps of every problem, all problems per launch, the nsteps launches
- * captured once in a HIP graph and replayed as one graph launch. Result in f_a
- * when nsteps is even, else f_b. step index starts at 0 on the first call and
- * continues across calls. */
+/* nsteps steps of every problem, all problems per launch, the launches captured
+ * once in a HIP graph and replayed as one graph launch. Two time steps per pass
+ * over the packed array (as lb_run) unless a problem has ny < 2 or
+ * lb_batch_set_tile asked for steps = 1; results are bitwise the same either way.
+ * Result in f_a when nsteps is even, else f_b. step index starts at 0 on the
+ * first call and continues across calls. */
 lb_status lb_step_batched(lb_batch* b, void* f_a, void* f_b, int32_t nsteps, void* stream);
 
 void lb_batch_destroy(lb_batch* b);

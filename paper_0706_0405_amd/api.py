@@ -275,8 +275,9 @@ class Batch:
         o = self.offsets[p]
         return buf[o:o + 9 * g.ny * self.pitches[p]].view(9, g.ny, self.pitches[p])
 
-    def set_tile(self, block_x):
-        check(lib().lb_batch_set_tile(self.h, ctypes.byref(LbTile(int(block_x), 0, 0))))
+    def set_tile(self, block_x, steps_per_pass=0):
+        """Threads per work item (64, 128, 256) and time steps per pass (0 = default, 1 or 2)."""
+        check(lib().lb_batch_set_tile(self.h, ctypes.byref(LbTile(int(block_x), 0, 0, int(steps_per_pass)))))
 
     def step(self, f_a, f_b, nsteps):
         """nsteps steps of every problem in one graph launch; returns the result buffer."""

@@ -1296,6 +1296,27 @@ __global__ __launch_bounds__(256) void k_step_batched(const KTConsts* __restrict
     march<false>(K, fi, fo, L, 0, K.ny, 0, 0);
 }
 
+// Two steps per pass of every problem (the two-step march over all rows of a
+// 60-column-per-wavefront strip; batched problems have no shock edges). Needs
+// ny >= 2 for every problem.
+template <typename S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_step2_batched(
+    const KTConsts* __restrict__ Ks, const ProbInfo* __restrict__ info, const WorkItem* __restrict__ items,
+    const S* fin, S* fout) {
+  const WorkItem w = items[blockIdx.x];
+  const KTConsts& K = Ks[w.prob];
+  const int64_t off = info[w.prob].offset;
+  const int lane = threadIdx.x & 63;
+  const int X0 = (w.strip * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6)) * 60;
+  if (X0 >= K.nx) return;
+  const View<S> fi = make_view<S>(K, fin + off), fo = make_view<S>(K, fout + off);
+  const Lane2 L = make_lane2<S>(K, X0, lane);
+  if (X0 == 0 || X0 + 62 >= K.nx)
+    march2<true>(K, fi, fo, L, 0, K.ny, 0, 0, 0, 0);
+  else
+    march2<false>(K, fi, fo, L, 0, K.ny, 0, 0, 0, 0);
+}
+
 // ------------------------------------------------------------------ host launch helpers
 
 static size_t elem_size(lb_prec p) { return p == LB_F32 ? 4 : 8; }
@@ -1737,6 +1758,9 @@ struct lb_batch {
   ProbInfo* d_info = nullptr;
   WorkItem* d_items = nullptr;
   int nitems = 0;
+  WorkItem* d_items2 = nullptr;   // work list of the two-step kernel (60-column wavefronts)
+  int nitems2 = 0;
+  int steps = 2;                  // time steps per pass: 2 when every problem has ny >= 2
   int64_t step = 0;
   // captured graph
   hipGraphExec_t exec = nullptr;
@@ -1744,6 +1768,7 @@ struct lb_batch {
   void* g_fb = nullptr;
   int g_nsteps = -1;
   int g_bx = 0;
+  int g_steps = 0;
   void* g_stream = nullptr;
 };
 
@@ -1754,16 +1779,31 @@ static lb_status batch_items(lb_batch* b) {
   for (int p = 0; p < b->nprob; ++p) order[p] = p;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int c) { return b->grids[a].nx * (int64_t)b->grids[a].ny > b->grids[c].nx * (int64_t)b->grids[c].ny; });
+  std::vector<WorkItem> items2;
+  const int wpb = b->block_x / 64;
   for (int p : order) {
     const int ns = (b->grids[p].nx + b->block_x - 1) / b->block_x;
     for (int s = 0; s < ns; ++s) items.push_back({p, s});
+    const int ns2 = ((b->grids[p].nx + 59) / 60 + wpb - 1) / wpb;
+    for (int s = 0; s < ns2; ++s) items2.push_back({p, s});
   }
   if (b->d_items) HIP_CHECK(hipFree(b->d_items));
-  b->d_items = nullptr;
+  if (b->d_items2) HIP_CHECK(hipFree(b->d_items2));
+  b->d_items = b->d_items2 = nullptr;
   HIP_CHECK(hipMalloc(&b->d_items, items.size() * sizeof(WorkItem)));
   HIP_CHECK(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+  HIP_CHECK(hipMalloc(&b->d_items2, items2.size() * sizeof(WorkItem)));
+  HIP_CHECK(hipMemcpy(b->d_items2, items2.data(), items2.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
   b->nitems = (int)items.size();
+  b->nitems2 = (int)items2.size();
   return LB_OK;
+}
+
+// Two steps per pass unless asked otherwise, or some problem has ny < 2.
+static int batch_default_steps(const lb_batch* b) {
+  for (const lb_grid& g : b->grids)
+    if (g.ny < 2) return 1;
+  return 2;
 }
 
 extern "C" lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, lb_prec prec, lb_batch** out) {
@@ -1814,6 +1854,7 @@ extern "C" lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, lb_pre
     lb_batch_destroy(b);
     return fail(LB_EHIP, "batch metadata upload failed");
   }
+  b->steps = batch_default_steps(b);
   if ((s = batch_items(b))) {
     lb_batch_destroy(b);
     return s;
@@ -1835,6 +1876,9 @@ extern "C" lb_status lb_batch_set_tile(lb_batch* b, const lb_tile* tile) {
   int bx = 256;
   if (tile && tile->block_x) bx = tile->block_x;
   if (bx != 64 && bx != 128 && bx != 256) return fail(LB_EINVAL, "tile block_x must be 64, 128 or 256");
+  const int sp = tile ? tile->steps : 0;
+  if (sp < 0 || sp > 2) return fail(LB_EINVAL, "tile steps must be 0, 1 or 2");
+  b->steps = (sp == 1 || batch_default_steps(b) == 1) ? 1 : 2;
   if (bx == b->block_x) return LB_OK;
   b->block_x = bx;
   return batch_items(b);
@@ -1851,6 +1895,31 @@ static lb_status launch_batched(lb_batch* b, const void* fin, void* fout, hipStr
   return LB_OK;
 }
 
+static lb_status launch_batched2(lb_batch* b, const void* fin, void* fout, hipStream_t st) {
+  if (b->prec == LB_F64)
+    hipLaunchKernelGGL(k_step2_batched<double>, dim3(b->nitems2), dim3(b->block_x), 0, st, b->d_consts, b->d_info,
+                       b->d_items2, (const double*)fin, (double*)fout);
+  else
+    hipLaunchKernelGGL(k_step2_batched<float>, dim3(b->nitems2), dim3(b->block_x), 0, st, b->d_consts, b->d_info,
+                       b->d_items2, (const float*)fin, (float*)fout);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
+// nsteps steps of the batch from fa (result in fa when nsteps is even): as
+// launch_steps, an even number of two-step passes after 0..3 single steps.
+static lb_status batched_steps(lb_batch* b, void* fa, void* fb, int nsteps, hipStream_t st) {
+  const int pairs = (b->steps == 2) ? (nsteps / 2) & ~1 : 0;
+  const int singles = nsteps - 2 * pairs;
+  int k = 0;
+  lb_status s;
+  for (int j = 0; j < singles; ++j, ++k)
+    if ((s = launch_batched(b, (k % 2 == 0) ? fa : fb, (k % 2 == 0) ? fb : fa, st))) return s;
+  for (int j = 0; j < pairs; ++j, ++k)
+    if ((s = launch_batched2(b, (k % 2 == 0) ? fa : fb, (k % 2 == 0) ? fb : fa, st))) return s;
+  return LB_OK;
+}
+
 extern "C" lb_status lb_step_batched(lb_batch* b, void* fa, void* fb, int32_t nsteps, void* stream) {
   if (!b) return fail(LB_EINVAL, "batch is NULL");
   lb_status s;
@@ -1861,19 +1930,16 @@ extern "C" lb_status lb_step_batched(lb_batch* b, void* fa, void* fb, int32_t ns
   hipStream_t st = (hipStream_t)stream;
   if (nsteps == 0) return LB_OK;
   if (st == nullptr) {
-    for (int n = 0; n < nsteps; ++n)
-      if ((s = launch_batched(b, (n % 2 == 0) ? fa : fb, (n % 2 == 0) ? fb : fa, st))) return s;
+    if ((s = batched_steps(b, fa, fb, nsteps, st))) return s;
     b->step += nsteps;
     return LB_OK;
   }
   if (!(b->exec && b->g_fa == fa && b->g_fb == fb && b->g_nsteps == nsteps && b->g_bx == b->block_x &&
-        b->g_stream == stream)) {
+        b->g_steps == b->steps && b->g_stream == stream)) {
     if (b->exec) HIP_CHECK(hipGraphExecDestroy(b->exec));
     b->exec = nullptr;
     HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    lb_status ls = LB_OK;
-    for (int n = 0; n < nsteps && ls == LB_OK; ++n)
-      ls = launch_batched(b, (n % 2 == 0) ? fa : fb, (n % 2 == 0) ? fb : fa, st);
+    const lb_status ls = batched_steps(b, fa, fb, nsteps, st);
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamEndCapture(st, &graph);
     if (ls != LB_OK) {
@@ -1888,6 +1954,7 @@ extern "C" lb_status lb_step_batched(lb_batch* b, void* fa, void* fb, int32_t ns
     b->g_fb = fb;
     b->g_nsteps = nsteps;
     b->g_bx = b->block_x;
+    b->g_steps = b->steps;
     b->g_stream = stream;
   }
   HIP_CHECK(hipGraphLaunch(b->exec, st));
@@ -1901,6 +1968,7 @@ extern "C" void lb_batch_destroy(lb_batch* b) {
   if (b->d_consts) (void)hipFree(b->d_consts);
   if (b->d_info) (void)hipFree(b->d_info);
   if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_items2) (void)hipFree(b->d_items2);
   delete b;
 }
 

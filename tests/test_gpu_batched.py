@@ -54,20 +54,43 @@ def test_layout_is_aligned_and_packed():
     assert B.total == prev_end
 
 
+@pytest.mark.parametrize("spp", [1, 2])
 @pytest.mark.parametrize("block_x", [64, 128, 256])
-def test_batched_equals_single_runs_bitwise(block_x):
+def test_batched_equals_single_runs_bitwise(block_x, spp):
+    """One or two steps per pass over the packed array; the reference is each problem
+    run alone, one step per launch."""
     cfgs, _ = P.batched(nprob=48, seed=2, steps=200)
     lb, grids, B, fa, fb, s = _make(cfgs)
-    B.set_tile(block_x)
+    B.set_tile(block_x, spp)
     with torch.cuda.stream(s):
         out = B.step(fa, fb, 200)
     torch.cuda.synchronize()
-    say("case batched tile", block_x)
+    say("case batched tile", block_x, "steps per pass", spp)
     for k, (c, g) in enumerate(zip(cfgs, grids)):
         f1 = lb.init(g, *_fields(c), prec="f32")
         f2 = lb.empty(g, "f32", DEV)
-        r = lb.run(g, f1, f2, 200, prec="f32")
+        r = lb.run(g, f1, f2, 200, prec="f32", steps_per_pass=1)
         assert torch.equal(_bits(r[:, :, :g.nx]), _bits(B.view(out, k)[:, :, :g.nx])), k
+
+
+@pytest.mark.parametrize("nsteps", [1, 3, 6, 7])
+def test_batched_step_counts_two_steps_per_pass(nsteps):
+    """Odd and even step counts (0-3 single steps before the two-step passes), both
+    precisions, without a graph (NULL stream) and with one."""
+    cfgs, _ = P.batched(nprob=10, seed=5, steps=nsteps)
+    for prec, graph in (("f32", True), ("f64", True), ("f32", False)):
+        lb, grids, B, fa, fb, s = _make(cfgs, prec)
+        ref_a = fa.clone()
+        if graph:
+            with torch.cuda.stream(s):
+                out = B.step(fa, fb, nsteps)
+        else:   # the default stream: launches without a graph
+            out = B.step(fa, fb, nsteps)
+        torch.cuda.synchronize()
+        for k, g in enumerate(grids):
+            f1 = B.view(ref_a, k).clone()
+            r = lb.run(g, f1, torch.empty_like(f1), nsteps, prec=prec, steps_per_pass=1)
+            assert torch.equal(_bits(r[:, :, :g.nx]), _bits(B.view(out, k)[:, :, :g.nx])), (prec, k)
 
 
 def test_graph_replays_continue_the_run():
