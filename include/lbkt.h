@@ -112,11 +112,13 @@ typedef struct {
 /* Launch shape of the step kernels. The grid is cut into tiles of block_x
  * columns (64, 128 or 256: one thread per column) by `rows` rows (>= 1).
  * blocks = 0 launches one block per tile; blocks > 0 launches that many
- * persistent blocks (rounded down to a multiple of 8), each looping over tiles.
- * All zero (or a NULL tile) = the default: 256 x 32 tiles, one block per tile,
- * shrunk on small grids (rows down to 2, then columns) to give at least 1024 tiles.
- * In the two-step pass a wavefront of 64 threads produces 62 columns, so a tile
- * is block_x / 64 * 62 columns wide. */
+ * persistent blocks (rounded down to a multiple of 8 where tiles are dealt to
+ * the XCDs in bands), each looping over tiles. All zero (or a NULL tile) = the
+ * default: 256 x 32 tiles, one block per tile, shrunk on small grids (rows down
+ * to 2, then columns) to give at least 1024 tiles; the two-step pass takes at
+ * most 12 rows (double) or 24 rows (float) by default. In the two-step pass a
+ * wavefront of 64 threads produces 60 columns, so a tile is block_x / 64 * 60
+ * columns wide. */
 typedef struct {
   int32_t block_x, rows, blocks;
   int32_t steps;   /* lb_run only: time steps per pass over the array, 1 or 2; 0 = the
