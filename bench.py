@@ -367,6 +367,11 @@ def bench_adjoint(dev, steps=2000):
         lb.run(g, fa, fb, steps, prec="f32")
         torch.cuda.synchronize()
         t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        fa = lb.init(g, rho, ux, uy, p, prec="f32")
+        lb.run(g, fa, fb, steps, prec="f32", steps_per_pass=1)
+        torch.cuda.synchronize()
+        t_fwd1 = time.perf_counter() - t0
         r0 = rho.clone().requires_grad_(True)
         R.loss_and_grad(r0, target)            # warm
         torch.cuda.synchronize()
@@ -376,6 +381,7 @@ def bench_adjoint(dev, steps=2000):
         t_grad = time.perf_counter() - t0
     return {"grid": [g.nx, g.ny], "steps": steps, "checkpoint_every": R.seg, "forward_ms": t_fwd * 1e3,
             "gradient_ms": t_grad * 1e3, "ratio": t_grad / t_fwd,
+            "forward_one_step_per_launch_ms": t_fwd1 * 1e3, "ratio_vs_one_step_forward": t_grad / t_fwd1,
             "grad_finite": bool(torch.isfinite(grad).all())}
 
 
