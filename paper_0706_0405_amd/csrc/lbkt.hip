@@ -1364,6 +1364,24 @@ static void default_tile(int nx, int ny, int* bx, int* rows) {
   *rows = r;
 }
 
+// Default launch shape of the two-step pass: 256 threads (4 x 60 columns) by
+// 12 rows (double) or 24 rows (float), the fastest measured on the 8192 x 2048
+// grid; on smaller grids the rows shrink (down to 2), then the columns, then
+// the rows to 1, until there are at least 1024 tiles (on small grids
+// parallelism outweighs the extra first-step rows of a short tile; measured on
+// the paper's 200x4 .. 960x240 configurations against the autotuner).
+static void default_tile2(int nx, int ny, lb_prec prec, int* bx, int* rows) {
+  auto ntiles = [&](int b, int r) {
+    return (int64_t)(((nx + 59) / 60 + b / 64 - 1) / (b / 64)) * ((ny + r - 1) / r);
+  };
+  int b = 256, r = prec == LB_F64 ? 12 : 24;
+  while (ntiles(b, r) < 1024 && r > 2) r = std::max(2, r / 2);
+  while (ntiles(b, r) < 1024 && b > 64) b /= 2;
+  if (ntiles(b, r) < 1024) r = 1;
+  *bx = b;
+  *rows = std::min(r, ny);
+}
+
 static lb_status resolve_tile(const lb_tile* tile, int nx, int ny, Tile* t) {
   int b, r, nb = 0;
   default_tile(nx, ny, &b, &r);
@@ -1422,10 +1440,8 @@ static lb_status launch_step(const lb_grid* g, const KTConsts& K, lb_prec prec, 
 static lb_status launch_step2(const lb_grid* g, const KTConsts& K, lb_prec prec, const void* fin, void* fout,
                               int64_t step, const Tile& t, hipStream_t st) {
   const bool w = wide(g, elem_size(prec));
-  const int bx = t.bx;
-  // default tile height of the two-step kernel: at most 12 rows (double) or 24
-  // (float), the fastest measured on the 8192 x 2048 grid (8..48 tried)
-  int rows = t.user ? t.rows : std::min(t.rows, prec == LB_F64 ? 12 : 24);
+  int bx = t.bx, rows = t.rows;
+  if (!t.user) default_tile2(g->nx, g->ny, prec, &bx, &rows);
   if (w) rows = std::min(rows, wide_max_rows(g, elem_size(prec)) - 2);   // >= 1 (launch_steps)
   const int wpb = bx / 64;
   const int nwaves = (g->nx + 59) / 60;   // 60 output columns per wavefront
@@ -1986,7 +2002,7 @@ extern "C" lb_status lb_autotune(const lb_grid* g, lb_prec prec, void* fa, void*
   HIP_CHECK(hipEventCreate(&e0));
   HIP_CHECK(hipEventCreate(&e1));
   const int bxs[3] = {64, 128, 256};
-  const int rws[7] = {4, 8, 12, 16, 24, 32, 64};
+  const int rws[9] = {1, 2, 4, 8, 12, 16, 24, 32, 64};
   const int nbs[3] = {0, 1024, 2048};
   float bestv = 1e30f;
   lb_tile bt = {256, 16, 0, 0};
@@ -1995,7 +2011,7 @@ extern "C" lb_status lb_autotune(const lb_grid* g, lb_prec prec, void* fa, void*
   // both kernels lb_run can use: one step per launch, and two per pass (ny >= 2)
   for (int sp = 1; sp <= (g->ny >= 2 ? 2 : 1); ++sp)
     for (int bi = 0; bi < 3; ++bi)
-      for (int ri = 0; ri < 7; ++ri)
+      for (int ri = 0; ri < 9; ++ri)
         for (int ni = 0; ni < 3; ++ni) {
           const int bx = bxs[bi], rows = std::min(rws[ri], g->ny);
           if (ri > 0 && rows == std::min(rws[ri - 1], g->ny)) continue;
@@ -2003,14 +2019,49 @@ extern "C" lb_status lb_autotune(const lb_grid* g, lb_prec prec, void* fa, void*
           auto launch = [&](const void* in, void* out) {
             return sp == 1 ? launch_step(g, K, prec, in, out, 0, t, st) : launch_step2(g, K, prec, in, out, 0, t, st);
           };
-          // warm-up launch, then reps timed launches
+          // warm-up launch, then reps timed launches: on a stream, captured in a
+          // graph and timed as one replay (as lb_run with use_graph runs them;
+          // on small grids the gaps between direct launches would dominate)
           if ((s = launch(fa, fb))) goto done;
-          if (hipEventRecord(e0, st) != hipSuccess) { s = fail(LB_EHIP, "event record"); goto done; }
-          for (int n = 0; n < reps; ++n)
-            if ((s = launch((n % 2 == 0) ? fb : fa, (n % 2 == 0) ? fa : fb))) goto done;
-          if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-            s = fail(LB_EHIP, "event sync");
-            goto done;
+          if (st != nullptr) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+              s = fail(LB_EHIP, "stream capture");
+              goto done;
+            }
+            lb_status ls = LB_OK;
+            for (int n = 0; n < reps && ls == LB_OK; ++n) ls = launch((n % 2 == 0) ? fb : fa, (n % 2 == 0) ? fa : fb);
+            const hipError_t ce = hipStreamEndCapture(st, &graph);
+            if (ls != LB_OK || ce != hipSuccess) {
+              if (graph) (void)hipGraphDestroy(graph);
+              s = ls != LB_OK ? ls : fail(LB_EHIP, "stream capture");
+              goto done;
+            }
+            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+              s = fail(LB_EHIP, "graph instantiate");
+              goto done;
+            }
+            hipError_t le = hipGraphLaunch(exec, st);   // warm replay
+            if (le == hipSuccess) le = hipEventRecord(e0, st);
+            if (le == hipSuccess) le = hipGraphLaunch(exec, st);
+            if (le == hipSuccess) le = hipEventRecord(e1, st);
+            if (le == hipSuccess) le = hipEventSynchronize(e1);
+            (void)hipGraphExecDestroy(exec);
+            if (le != hipSuccess) {
+              s = fail(LB_EHIP, "graph replay");
+              goto done;
+            }
+          } else {
+            if (hipEventRecord(e0, st) != hipSuccess) { s = fail(LB_EHIP, "event record"); goto done; }
+            for (int n = 0; n < reps; ++n)
+              if ((s = launch((n % 2 == 0) ? fb : fa, (n % 2 == 0) ? fa : fb))) goto done;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+              s = fail(LB_EHIP, "event sync");
+              goto done;
+            }
           }
           float ms = 0.f;
           (void)hipEventElapsedTime(&ms, e0, e1);
