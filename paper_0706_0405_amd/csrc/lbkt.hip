@@ -227,8 +227,9 @@ static int shock_cells(const lb_grid* g, int e, int64_t step) {
 // larger ones get one resource per plane over the rows a tile touches (ViewG).
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 #define LB_RSRC_WORD3 0x00020000
-// cache policy of the distribution stores: non-temporal (the next step reads
-// them only after the whole array has streamed through the caches)
+// cache policy of the distribution stores (default of the views): non-temporal
+// (the next step reads them only after the whole array has streamed through
+// the caches); the step kernels pick theirs per precision (see k_step, k_step2)
 #ifndef LB_STORE_AUX
 #define LB_STORE_AUX 2
 #endif
@@ -255,17 +256,18 @@ template <> struct Mem<double> {
   static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vb, (int)sb, 0));
   }
+  template <int AUX = LB_STORE_AUX>
   static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vb, (int)sb, LB_STORE_AUX);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vb, (int)sb, AUX);
   }
 };
 template <> struct Mem<float> {
   static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
     return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vb, (int)sb, 0));
   }
+  template <int AUX = LB_STORE_AUX>
   static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb, double v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)v), r, (int)vb, (int)sb,
-                                          LB_STORE_AUX);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)v), r, (int)vb, (int)sb, AUX);
   }
 };
 
@@ -275,8 +277,8 @@ __device__ __forceinline__ S ld_raw(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint3
 // A distribution array below 4 GiB viewed through a buffer resource. Values are
 // addressed by (plane i, row y, byte offset vb of the column in the row); the
 // row and the column go into the lane's 32-bit offset, the plane into the
-// scalar offset.
-template <typename S>
+// scalar offset. AUX: the cache policy of the stores.
+template <typename S, int AUX = LB_STORE_AUX>
 struct View {
   using Sto = S;
   __amdgpu_buffer_rsrc_t r;
@@ -298,14 +300,14 @@ struct View {
   __device__ __forceinline__ void store9(int y, uint32_t vb, const double v[9]) const {
     const uint32_t o = (uint32_t)y * rowB + vb;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Mem<S>::st(r, o, (uint32_t)i * planeB, v[i]);
+    for (int i = 0; i < 9; ++i) Mem<S>::template st<AUX>(r, o, (uint32_t)i * planeB, v[i]);
   }
   __device__ __forceinline__ void load9_any(int y, uint32_t vb, double v[9]) const { load9(y, vb, v); }
 };
 
-template <typename S>
-__device__ __forceinline__ View<S> make_view(const KTConsts& K, const void* p) {
-  View<S> v;
+template <typename S, int AUX = LB_STORE_AUX>
+__device__ __forceinline__ View<S, AUX> make_view(const KTConsts& K, const void* p) {
+  View<S, AUX> v;
   v.rowB = (uint32_t)(K.pitch * sizeof(S));
   v.planeB = (uint32_t)(K.plane * sizeof(S));
   v.r = make_rsrc(p, v.planeB * 9u);
@@ -921,7 +923,11 @@ template <typename S, bool WIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_step2(
     KTConsts K, const S* __restrict__ fin, S* __restrict__ fout, int rows, int nstrips, int ntiles, int xcd_map,
     int ish_lo, int ish_hi, int ish2_lo, int ish2_hi) {
-  const View<S> fi0 = make_view<S>(K, fin), fo0 = make_view<S>(K, fout);
+  // stores: non-temporal for double, ordinary for float storage (float: 0.164
+  // vs 0.168-0.174 ms per step on the 8192 x 2048 grid on two devices; double:
+  // equal)
+  constexpr int AUX = sizeof(S) == 8 ? 2 : 0;
+  const View<S, AUX> fi0 = make_view<S, AUX>(K, fin), fo0 = make_view<S, AUX>(K, fout);
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
   for (int id = blockIdx.x; id < ntiles; id += gridDim.x) {
