@@ -1315,7 +1315,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int lane = threadIdx.x & 63;
   const int X0 = (w.strip * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6)) * 60;
   if (X0 >= K.nx) return;
-  const View<S> fi = make_view<S>(K, fin + off), fo = make_view<S>(K, fout + off);
+  constexpr int AUX = sizeof(S) == 8 ? 2 : 0;   // the stores of k_step2
+  const View<S, AUX> fi = make_view<S, AUX>(K, fin + off), fo = make_view<S, AUX>(K, fout + off);
   const Lane2 L = make_lane2<S>(K, X0, lane);
   if (X0 == 0 || X0 + 62 >= K.nx)
     march2<true>(K, fi, fo, L, 0, K.ny, 0, 0, 0, 0);
