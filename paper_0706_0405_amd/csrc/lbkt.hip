@@ -943,6 +943,20 @@ __device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& 
   }
 }
 
+// The grid constants of a kernel whose first argument is its KTConsts (offset 0
+// of the kernel-argument segment), re-read through a pointer that the compiler
+// cannot see through. Loads through it stay scalar and invariant (constant
+// address space), so the register allocator re-issues them (s_load) where the
+// march loops run short of SGPRs, instead of spilling the ~70 SGPRs of constants
+// to VGPR lanes and reloading them with v_readlane, which are VALU instructions
+// (float-storage two-step loop: 1308 instead of 1479 VALU instructions per
+// three rows).
+__device__ __forceinline__ const KTConsts& kernarg_consts() {
+  auto kp = (const __attribute__((address_space(4))) KTConsts*)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(kp));
+  return *(const KTConsts*)kp;
+}
+
 template <typename S, bool WIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_step2(
     KTConsts K, const S* __restrict__ fin, S* __restrict__ fout, int rows, int nstrips, int ntiles, int xcd_map,
@@ -972,10 +986,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       else
         march2<false>(K, fi, fo, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
     } else {
+      const KTConsts& KM = kernarg_consts();   // K itself, for the march loops
       if (edge)
-        march2<true>(K, fi0, fo0, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
+        march2<true>(KM, fi0, fo0, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
       else
-        march2<false>(K, fi0, fo0, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
+        march2<false>(KM, fi0, fo0, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
     }
   }
 }
@@ -1272,10 +1287,11 @@ __global__ __launch_bounds__(256) void k_adjoint(KTConsts K, const S* __restrict
   } else {
     const View<S> ff = make_view<S>(K, fn);
     const View<double> gi = make_view<double>(K, g1), go = make_view<double>(K, g0);
+    const KTConsts& KM = kernarg_consts();   // K itself, for the march loops
     if (xw0 == 0 || xw0 + 64 >= K.nx)
-      adj_march<true>(K, ff, gi, go, xw0, lane, y0, y1);
+      adj_march<true>(KM, ff, gi, go, xw0, lane, y0, y1);
     else
-      adj_march<false>(K, ff, gi, go, xw0, lane, y0, y1);
+      adj_march<false>(KM, ff, gi, go, xw0, lane, y0, y1);
   }
 }
 
