@@ -186,7 +186,12 @@ lb_status lb_step_adjoint(const lb_grid* grid, lb_prec prec, const void* f_n, co
 
 /* nsteps steps from f0, keeping every state: out[j] (a host array of nsteps
  * device pointers, each a distribution array of the storage type) receives the
- * state after step step0 + j. Used to recompute a checkpointed segment. */
+ * state after step step0 + j. Used to recompute a checkpointed segment.
+ * Consecutive arrays (f0, out[0]; out[j], out[j+1]) must not overlap
+ * (LB_EALIAS). Steps run two per pass, the first step's state stored on the way
+ * (bitwise the state of a single step), wherever the pass's input and both of
+ * its outputs are distinct arrays below 4 GiB and ny >= 2; elsewhere one step
+ * per launch. */
 lb_status lb_run_record(const lb_grid* grid, lb_prec prec, const void* f0, void* const* out, int64_t step0,
                         int32_t nsteps, void* stream);
 

@@ -825,18 +825,35 @@ __device__ __forceinline__ void f1_row_periodic(const KTConsts& K, const V& fi, 
   row_first<XEDGE>(K, fi, L, q, pd, cd, nd, t);
 }
 
+// Where the intermediate state f1 goes: NoRec drops it (lb_run); Rec stores the
+// f1 rows [y0, y1) of the tile through its view (lb_run_record, which keeps
+// every state). f1 is already rounded to the storage type, so the stored state
+// is bitwise that of a single step.
+struct NoRec {
+  __device__ __forceinline__ void put(int, const Lane2&, const double*) const {}
+};
+template <class V>
+struct Rec {
+  V v;
+  int y0, y1;
+  __device__ __forceinline__ void put(int y, const Lane2& L, const double t[9]) const {
+    if (y >= y0 && y < y1 && L.out) v.store9(y, L.vbo, t);
+  }
+};
+
 // One row of the two-step march: issue the fetch of f0 row y+3 (F), compute f1
 // of row y (N: f0 row y+1, fetched two rows earlier), then the second step of
 // row y-1 from f1 rows y-2, y-1 (q0, q1) and y; shift the windows.
-template <bool XEDGE, class V>
+template <bool XEDGE, class V, class R>
 __device__ __forceinline__ void march2_row(const KTConsts& K, const V& fi, const V& fo, const Lane2& L, int y,
                                            int ylast, double pd[9], double cd[9], Sto<V> q0[9], Sto<V> q1[9],
-                                           const Sto<V> N[9], Sto<V> F[9]) {
+                                           const Sto<V> N[9], Sto<V> F[9], const R& rec) {
   fi.raw9(min(y + 3, ylast), L.vbx, F);
   double nd[9], t[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) nd[i] = widen(N[i]);
   row_first<XEDGE>(K, fi, L, y, pd, cd, nd, t);
+  rec.put(y, L, t);
   __builtin_amdgcn_sched_barrier(0);   // the two updates one after the other (register pressure)
   row_second<XEDGE>(K, fo, L, y - 1, q0, q1, t);
 #pragma unroll
@@ -855,9 +872,9 @@ __device__ __forceinline__ void march2_row(const KTConsts& K, const V& fi, const
 // the grid); after f1 row y the second step of row y-1 follows. Rows ya and
 // ya+1 prime the f1 window (yb >= ya+1 always holds), after which the register
 // sets are in the same state for every tile.
-template <bool XEDGE, class V>
+template <bool XEDGE, class V, class R>
 __device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& fo, const Lane2& L, int y0, int y1,
-                                       int ish_lo, int ish_hi, int ish2_lo, int ish2_hi) {
+                                       int ish_lo, int ish_hi, int ish2_lo, int ish2_hi, const R& rec) {
   using S = Sto<V>;
   const int ny = K.ny;
   const bool pery = (K.kind[2] == BC_PERIODIC);
@@ -877,6 +894,7 @@ __device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& 
 #pragma unroll
   for (int i = 0; i < 9; ++i) nd[i] = widen(N0[i]);
   row_first<XEDGE>(K, fi, L, ya, pd, cd, nd, t);
+  rec.put(ya, L, t);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     q0[i] = (S)t[i];
@@ -892,6 +910,7 @@ __device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& 
     ghost_row<3>(K, fi, L.xs, L.vbx, ish_hi, nd);
   }
   row_first<XEDGE>(K, fi, L, ya + 1, pd, cd, nd, t);
+  rec.put(ya + 1, L, t);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     q1[i] = (S)t[i];
@@ -911,21 +930,22 @@ __device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& 
   // with period three (the loop is unrolled by three).
   int y = ya + 2;
   for (; y + 2 < ylast; y += 3) {
-    march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N2, N1);
-    march2_row<XEDGE>(K, fi, fo, L, y + 1, ylast, pd, cd, q0, q1, N0, N2);
-    march2_row<XEDGE>(K, fi, fo, L, y + 2, ylast, pd, cd, q0, q1, N1, N0);
+    march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N2, N1, rec);
+    march2_row<XEDGE>(K, fi, fo, L, y + 1, ylast, pd, cd, q0, q1, N0, N2, rec);
+    march2_row<XEDGE>(K, fi, fo, L, y + 2, ylast, pd, cd, q0, q1, N1, N0, rec);
   }
   if (y < ylast) {
-    march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N2, N1);
+    march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N2, N1, rec);
     y += 1;
     if (y < ylast) {
-      march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N0, N2);
+      march2_row<XEDGE>(K, fi, fo, L, y, ylast, pd, cd, q0, q1, N0, N2, rec);
       y += 1;
     }
   }
   if (y <= yb) {   // y = ny-1: the upper f0 neighbour is the top ghost
     ghost_row<3>(K, fi, L.xs, L.vbx, ish_hi, nd);
     row_first<XEDGE>(K, fi, L, y, pd, cd, nd, t);
+    rec.put(y, L, t);
     row_second<XEDGE>(K, fo, L, y - 1, q0, q1, t);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -957,10 +977,13 @@ __device__ __forceinline__ const KTConsts& kernarg_consts() {
   return *(const KTConsts*)kp;
 }
 
-template <typename S, bool WIDE>
+// REC: also store the intermediate state f1 to f1out (lb_run_record; arrays
+// below 4 GiB only).
+template <typename S, bool WIDE, bool REC = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_step2(
-    KTConsts K, const S* __restrict__ fin, S* __restrict__ fout, int rows, int nstrips, int ntiles, int xcd_map,
-    int ish_lo, int ish_hi, int ish2_lo, int ish2_hi) {
+    KTConsts K, const S* __restrict__ fin, S* __restrict__ fout, S* __restrict__ f1out, int rows, int nstrips,
+    int ntiles, int xcd_map, int ish_lo, int ish_hi, int ish2_lo, int ish2_hi) {
+  static_assert(!(WIDE && REC), "recording runs on arrays below 4 GiB");
   // stores: non-temporal for double, ordinary for float storage (float: 0.164
   // vs 0.168-0.174 ms per step on the 8192 x 2048 grid on two devices; double:
   // equal)
@@ -982,15 +1005,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       const ViewG<S> fi = make_view_g_rows<S>(K, fin, y0 - 2, y1 + 1);
       const ViewG<S> fo = make_view_g_rows<S>(K, fout, y0, y1 - 1);
       if (edge)
-        march2<true>(K, fi, fo, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
+        march2<true>(K, fi, fo, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi, NoRec{});
       else
-        march2<false>(K, fi, fo, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
+        march2<false>(K, fi, fo, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi, NoRec{});
     } else {
       const KTConsts& KM = kernarg_consts();   // K itself, for the march loops
-      if (edge)
-        march2<true>(KM, fi0, fo0, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
-      else
-        march2<false>(KM, fi0, fo0, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi);
+      if constexpr (REC) {
+        const Rec<View<S, AUX>> rec{make_view<S, AUX>(K, f1out), y0, y1};
+        if (edge)
+          march2<true>(KM, fi0, fo0, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi, rec);
+        else
+          march2<false>(KM, fi0, fo0, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi, rec);
+      } else {
+        if (edge)
+          march2<true>(KM, fi0, fo0, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi, NoRec{});
+        else
+          march2<false>(KM, fi0, fo0, L, y0, y1, ish_lo, ish_hi, ish2_lo, ish2_hi, NoRec{});
+      }
     }
   }
 }
@@ -1360,9 +1391,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const View<S, AUX, false> fi = make_view<S, AUX, false>(K, fin + off), fo = make_view<S, AUX, false>(K, fout + off);
   const Lane2 L = make_lane2<S>(K, X0, lane);
   if (X0 == 0 || X0 + 62 >= K.nx)
-    march2<true>(K, fi, fo, L, 0, K.ny, 0, 0, 0, 0);
+    march2<true>(K, fi, fo, L, 0, K.ny, 0, 0, 0, 0, NoRec{});
   else
-    march2<false>(K, fi, fo, L, 0, K.ny, 0, 0, 0, 0);
+    march2<false>(K, fi, fo, L, 0, K.ny, 0, 0, 0, 0, NoRec{});
 }
 
 // ------------------------------------------------------------------ host launch helpers
@@ -1485,8 +1516,9 @@ static lb_status launch_step(const lb_grid* g, const KTConsts& K, lb_prec prec, 
 }
 
 // Two steps f_out = S(S(f_in)) at time indices step, step+1 in one pass.
+// f1out: also store the state after the first step there (arrays below 4 GiB).
 static lb_status launch_step2(const lb_grid* g, const KTConsts& K, lb_prec prec, const void* fin, void* fout,
-                              int64_t step, const Tile& t, hipStream_t st) {
+                              int64_t step, const Tile& t, hipStream_t st, void* f1out = nullptr) {
   const bool w = wide(g, elem_size(prec));
   int bx = t.bx, rows = t.rows;
   if (!t.user) default_tile2(g->nx, g->ny, prec, &bx, &rows);
@@ -1503,14 +1535,15 @@ static lb_status launch_step2(const lb_grid* g, const KTConsts& K, lb_prec prec,
   if (t.blocks > 0 && t.blocks < ntiles) nblocks = xcd_map ? std::max(8, t.blocks & ~7) : t.blocks;
   const int ish_lo = shock_cells(g, 2, step), ish_hi = shock_cells(g, 3, step);
   const int ish2_lo = shock_cells(g, 2, step + 1), ish2_hi = shock_cells(g, 3, step + 1);
+  if (f1out && w) return fail(LB_EUNSUPPORTED, "recording two steps per pass needs an array below 4 GiB");
   if (prec == LB_F64) {
-    auto kern = w ? k_step2<double, true> : k_step2<double, false>;
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fin, (double*)fout, rows, nstrips,
-                       ntiles, xcd_map, ish_lo, ish_hi, ish2_lo, ish2_hi);
+    auto kern = f1out ? k_step2<double, false, true> : w ? k_step2<double, true> : k_step2<double, false>;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fin, (double*)fout,
+                       (double*)f1out, rows, nstrips, ntiles, xcd_map, ish_lo, ish_hi, ish2_lo, ish2_hi);
   } else {
-    auto kern = w ? k_step2<float, true> : k_step2<float, false>;
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(bx), 0, st, K, (const float*)fin, (float*)fout, rows, nstrips,
-                       ntiles, xcd_map, ish_lo, ish_hi, ish2_lo, ish2_hi);
+    auto kern = f1out ? k_step2<float, false, true> : w ? k_step2<float, true> : k_step2<float, false>;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(bx), 0, st, K, (const float*)fin, (float*)fout, (float*)f1out,
+                       rows, nstrips, ntiles, xcd_map, ish_lo, ish_hi, ish2_lo, ish2_hi);
   }
   HIP_CHECK(hipGetLastError());
   return LB_OK;
@@ -1790,8 +1823,19 @@ extern "C" lb_status lb_run_record(const lb_grid* g, lb_prec prec, const void* f
   KTConsts K;
   build_consts(g, &K);
   hipStream_t st = (hipStream_t)stream;
-  for (int j = 0; j < nsteps; ++j)
-    if ((s = launch_step(g, K, prec, (j == 0) ? f0 : out[j - 1], out[j], step0 + j, t, st))) return s;
+  // two steps per pass (the first step's state stored on the way) where the
+  // input and both outputs are distinct arrays, else one step per launch
+  const bool two = (t.steps == 2) && !wide(g, elem_size(prec));
+  for (int j = 0; j < nsteps;) {
+    const void* in = (j == 0) ? f0 : out[j - 1];
+    if (two && j + 1 < nsteps && !overlap(in, bytes, out[j + 1], bytes) && !overlap(out[j], bytes, out[j + 1], bytes)) {
+      if ((s = launch_step2(g, K, prec, in, out[j + 1], step0 + j, t, st, out[j]))) return s;
+      j += 2;
+    } else {
+      if ((s = launch_step(g, K, prec, in, out[j], step0 + j, t, st))) return s;
+      j += 1;
+    }
+  }
   return LB_OK;
 }
 
