@@ -1377,10 +1377,61 @@ __global__ __launch_bounds__(256) void k_step_batched(const KTConsts* __restrict
 // Two steps per pass of every problem (the two-step march over all rows of a
 // 60-column-per-wavefront strip; batched problems have no shock edges). Needs
 // ny >= 2 for every problem.
-template <typename S>
+// Two steps on a strip of a 4-row grid with a periodic y axis (the batched
+// Riemann problems): the four f0 rows are fetched together, f1 of each row is
+// computed once from its periodic neighbours in registers (the general march
+// recomputes the far rows for the y ghosts: 6 first-step rows per 4 output rows)
+// and the four second-step rows follow. Same per-row updates as march2, so the
+// result is bitwise the same.
+template <bool XEDGE, class V>
+__device__ __forceinline__ void march2_ny4(const KTConsts& K, const V& fi, const V& fo, const Lane2& L) {
+  using S = Sto<V>;
+  S r0[9], r1[9], r2[9], r3[9];
+  fi.raw9(0, L.vbx, r0);
+  fi.raw9(1, L.vbx, r1);
+  fi.raw9(2, L.vbx, r2);
+  fi.raw9(3, L.vbx, r3);
+  double d0[9], d1[9], d2[9], d3[9], t[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    d0[i] = widen(r0[i]);
+    d1[i] = widen(r1[i]);
+    d2[i] = widen(r2[i]);
+    d3[i] = widen(r3[i]);
+  }
+  // one row at a time (the barriers keep the rows' temporaries from overlapping)
+  S q0[9], q1[9], q2[9], q3[9];   // f1 rows 0..3, rounded to the storage type
+  row_first<XEDGE>(K, fi, L, 0, d3, d0, d1, t);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) q0[i] = (S)t[i];
+  __builtin_amdgcn_sched_barrier(0);
+  row_first<XEDGE>(K, fi, L, 1, d0, d1, d2, t);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) q1[i] = (S)t[i];
+  __builtin_amdgcn_sched_barrier(0);
+  row_first<XEDGE>(K, fi, L, 2, d1, d2, d3, t);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) q2[i] = (S)t[i];
+  __builtin_amdgcn_sched_barrier(0);
+  row_first<XEDGE>(K, fi, L, 3, d2, d3, d0, t);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) q3[i] = (S)t[i];
+  __builtin_amdgcn_sched_barrier(0);
+  row_second<XEDGE>(K, fo, L, 0, q3, q0, q1);
+  __builtin_amdgcn_sched_barrier(0);
+  row_second<XEDGE>(K, fo, L, 1, q0, q1, q2);
+  __builtin_amdgcn_sched_barrier(0);
+  row_second<XEDGE>(K, fo, L, 2, q1, q2, q3);
+  __builtin_amdgcn_sched_barrier(0);
+  row_second<XEDGE>(K, fo, L, 3, q2, q3, q0);
+}
+
+template <typename S, bool NY4>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_step2_batched(
     const KTConsts* __restrict__ Ks, const ProbInfo* __restrict__ info, const WorkItem* __restrict__ items,
     const S* fin, S* fout) {
+  // NY4: every problem of the batch has 4 rows and a periodic y axis (a kernel of
+  // its own, so that the general march keeps its register allocation)
   const WorkItem w = items[blockIdx.x];
   const KTConsts& K = Ks[w.prob];
   const int64_t off = info[w.prob].offset;
@@ -1390,10 +1441,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   constexpr int AUX = sizeof(S) == 8 ? 2 : 0;   // the stores of k_step2
   const View<S, AUX, false> fi = make_view<S, AUX, false>(K, fin + off), fo = make_view<S, AUX, false>(K, fout + off);
   const Lane2 L = make_lane2<S>(K, X0, lane);
-  if (X0 == 0 || X0 + 62 >= K.nx)
+  const bool edge = (X0 == 0 || X0 + 62 >= K.nx);
+  if constexpr (NY4) {
+    if (edge)
+      march2_ny4<true>(K, fi, fo, L);
+    else
+      march2_ny4<false>(K, fi, fo, L);
+  } else if (edge) {
     march2<true>(K, fi, fo, L, 0, K.ny, 0, 0, 0, 0, NoRec{});
-  else
+  } else {
     march2<false>(K, fi, fo, L, 0, K.ny, 0, 0, 0, 0, NoRec{});
+  }
 }
 
 // ------------------------------------------------------------------ host launch helpers
@@ -1869,6 +1927,7 @@ struct lb_batch {
   WorkItem* d_items2 = nullptr;   // work list of the two-step kernel (60-column wavefronts)
   int nitems2 = 0;
   int steps = 2;                  // time steps per pass: 2 when every problem has ny >= 2
+  bool all_ny4 = false;           // every problem has 4 rows and a periodic y axis
   int64_t step = 0;
   // captured graph
   hipGraphExec_t exec = nullptr;
@@ -1980,6 +2039,9 @@ extern "C" lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, lb_pre
     return fail(LB_EHIP, "batch metadata upload failed");
   }
   b->steps = batch_default_steps(b);
+  b->all_ny4 = true;
+  for (int p = 0; p < b->nprob; ++p)
+    b->all_ny4 = b->all_ny4 && b->grids[p].ny == 4 && b->grids[p].edge[2].kind == LB_BC_PERIODIC;
   if ((s = batch_items(b))) {
     lb_batch_destroy(b);
     return s;
@@ -2021,12 +2083,15 @@ static lb_status launch_batched(lb_batch* b, const void* fin, void* fout, hipStr
 }
 
 static lb_status launch_batched2(lb_batch* b, const void* fin, void* fout, hipStream_t st) {
-  if (b->prec == LB_F64)
-    hipLaunchKernelGGL(k_step2_batched<double>, dim3(b->nitems2), dim3(b->block_x), 0, st, b->d_consts, b->d_info,
-                       b->d_items2, (const double*)fin, (double*)fout);
-  else
-    hipLaunchKernelGGL(k_step2_batched<float>, dim3(b->nitems2), dim3(b->block_x), 0, st, b->d_consts, b->d_info,
-                       b->d_items2, (const float*)fin, (float*)fout);
+  if (b->prec == LB_F64) {
+    auto kern = b->all_ny4 ? k_step2_batched<double, true> : k_step2_batched<double, false>;
+    hipLaunchKernelGGL(kern, dim3(b->nitems2), dim3(b->block_x), 0, st, b->d_consts, b->d_info, b->d_items2,
+                       (const double*)fin, (double*)fout);
+  } else {
+    auto kern = b->all_ny4 ? k_step2_batched<float, true> : k_step2_batched<float, false>;
+    hipLaunchKernelGGL(kern, dim3(b->nitems2), dim3(b->block_x), 0, st, b->d_consts, b->d_info, b->d_items2,
+                       (const float*)fin, (float*)fout);
+  }
   HIP_CHECK(hipGetLastError());
   return LB_OK;
 }

@@ -161,3 +161,59 @@ def test_autotuners_pick_valid_shapes_and_keep_results(tmp_path, monkeypatch):
         assert bx in (64, 128, 256)
     finally:
         B.close()
+
+
+def _ref_runs(lb, grids, B, src, nsteps, prec):
+    """Each problem run alone from the same input, one step per launch."""
+    out = []
+    for k, g in enumerate(grids):
+        f1 = B.view(src, k).clone()
+        out.append(lb.run(g, f1, torch.empty_like(f1), nsteps, prec=prec, steps_per_pass=1).clone())
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_four_row_periodic_batches_every_x_edge(prec):
+    """Batches whose problems all have 4 rows and a periodic y axis take a kernel of
+    their own (the four rows of a strip in registers); x edges of every kind but
+    the moving shock, split edges, ragged widths around the 60-column strips, odd
+    and even step counts: bitwise equal to each problem run alone."""
+    from tests.test_gpu_parity import _edge, _smooth_cfg
+    per = _edge("periodic")
+    xedges = [(_edge("outflow"), _edge("outflow")), (_edge("wall", split=2), _edge("inflow")),
+              (per, per), (_edge("inflow"), _edge("wall")), (_edge("outflow", split=1), _edge("wall", split=3))]
+    widths = [61, 3, 130, 250, 62, 8, 121, 1]
+    cfgs = [_smooth_cfg(nx, 4, [*xedges[k % len(xedges)], per, per], seed=k) for k, nx in enumerate(widths)]
+    for nsteps in (5, 6):
+        lb, grids, B, fa, fb, s = _make(cfgs, prec)
+        src = fa.clone()
+        with torch.cuda.stream(s):
+            out = B.step(fa, fb, nsteps)
+        torch.cuda.synchronize()
+        ref = _ref_runs(lb, grids, B, src, nsteps, prec)
+        for k, g in enumerate(grids):
+            assert torch.isfinite(ref[k][:, :, :g.nx]).all()
+            assert torch.equal(_bits(ref[k][:, :, :g.nx]), _bits(B.view(out, k)[:, :, :g.nx])), (nsteps, k)
+        B.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_mixed_batch_takes_the_general_march(prec):
+    """One problem that is not 4 rows with a periodic y axis sends the whole batch
+    through the general two-step march; still bitwise equal to single runs."""
+    from tests.test_gpu_parity import BC_SETS, _edge, _smooth_cfg
+    per = _edge("periodic")
+    cfgs = [_smooth_cfg(90, 4, [_edge("outflow"), _edge("outflow"), per, per], seed=1),
+            _smooth_cfg(77, 13, BC_SETS["walls"], seed=2),
+            _smooth_cfg(64, 4, BC_SETS["walls_split"], seed=3),
+            _smooth_cfg(125, 7, BC_SETS["inflow"], seed=4),
+            _smooth_cfg(30, 2, BC_SETS["periodic"], seed=5)]
+    lb, grids, B, fa, fb, s = _make(cfgs, prec)
+    src = fa.clone()
+    with torch.cuda.stream(s):
+        out = B.step(fa, fb, 7)
+    torch.cuda.synchronize()
+    ref = _ref_runs(lb, grids, B, src, 7, prec)
+    for k, g in enumerate(grids):
+        assert torch.equal(_bits(ref[k][:, :, :g.nx]), _bits(B.view(out, k)[:, :, :g.nx])), k
+    B.close()
