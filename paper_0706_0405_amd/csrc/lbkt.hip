@@ -1502,7 +1502,7 @@ static void default_tile(int nx, int ny, int* bx, int* rows, int min_tiles = 102
 }
 
 // Default launch shape of the two-step pass: 256 threads (4 x 60 columns) by
-// 12 rows (double) or 24 rows (float), the fastest measured on the 8192 x 2048
+// 11 rows (double) or 24 rows (float), the fastest measured on the 8192 x 2048
 // grid; on smaller grids the rows shrink (down to 2), then the columns, then
 // the rows to 1, until there are at least 1024 tiles (on small grids
 // parallelism outweighs the extra first-step rows of a short tile; measured on
@@ -1511,7 +1511,7 @@ static void default_tile2(int nx, int ny, lb_prec prec, int* bx, int* rows) {
   auto ntiles = [&](int b, int r) {
     return (int64_t)(((nx + 59) / 60 + b / 64 - 1) / (b / 64)) * ((ny + r - 1) / r);
   };
-  int b = 256, r = prec == LB_F64 ? 12 : 24;
+  int b = 256, r = prec == LB_F64 ? 11 : 24;
   while (ntiles(b, r) < 1024 && r > 2) r = std::max(2, r / 2);
   while (ntiles(b, r) < 1024 && b > 64) b /= 2;
   if (ntiles(b, r) < 1024) r = 1;
