@@ -138,6 +138,27 @@ def test_alias_and_alignment_rejected_before_launch():
     assert L.lb_status_str(-4) == b"LB_ENONFINITE"
 
 
+def test_run_record_arguments_rejected_before_launch():
+    """lb_run_record checks every output (alignment, overlap of consecutive states)
+    before its first launch."""
+    L = _lib.lib()
+    g = _grid().c()
+    f0 = ctypes.c_void_p(1 << 20)   # never dereferenced
+    A, B, C = 1 << 30, 1 << 31, 1 << 32
+
+    def outs(*ptrs):
+        return (ctypes.c_void_p * len(ptrs))(*[ctypes.c_void_p(p) for p in ptrs])
+
+    assert L.lb_run_record(ctypes.byref(g), 0, f0, outs(A), 0, -1, None) == -1
+    assert L.lb_run_record(ctypes.byref(g), 0, f0, None, 0, 2, None) == -1
+    st = L.lb_run_record(ctypes.byref(g), 0, f0, outs(A, B + 8, C), 0, 3, None)
+    assert st == -1 and b"aligned" in L.lb_last_error()
+    st = L.lb_run_record(ctypes.byref(g), 0, f0, outs(A, B, B), 0, 3, None)
+    assert st == -3 and b"overlap" in L.lb_last_error()
+    st = L.lb_run_record(ctypes.byref(g), 0, f0, outs(1 << 20, A), 0, 2, None)
+    assert st == -3 and b"overlap" in L.lb_last_error()
+
+
 def test_array_elems():
     g = _grid(nx=100, ny=4).c()
     assert g.pitch == 128
