@@ -451,7 +451,7 @@ def main():
     ap.add_argument("--prec", choices=["f64", "f32", "both"], default="both")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     args.steps += (-args.steps) % 4   # all two-step passes (their count even), result in the first buffer
