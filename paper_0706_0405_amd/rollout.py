@@ -6,7 +6,11 @@ reverse sweep uses the hand-written adjoint kernels: lb_step_adjoint for each
 step (in reverse order) and lb_init_adjoint for the initial map. Only every
 `seg`-th state is kept during the forward sweep (seg ~ sqrt(N)); the reverse
 sweep recomputes one segment at a time from its checkpoint, so memory is
-O(sqrt(N)) states for O(2N) forward steps.
+O(sqrt(N)) states for O(2N) forward steps. With keep_all=True every state is
+kept instead (N + 1 arrays; a 2000-step FP32 rollout of a 960 x 240 grid takes
+16.6 GB of device memory): the forward records them two steps per pass and the
+reverse sweep needs no recomputation. The recorded states are bitwise those the
+recomputation produces, so both ways give the same gradient bit for bit.
 """
 from __future__ import annotations
 
@@ -20,11 +24,12 @@ from . import api
 class Rollout:
     """N-step rollout of one grid with fixed initial velocity and pressure fields."""
 
-    def __init__(self, grid: api.Grid, ux0, uy0, p0, nsteps: int, prec="f32", seg=None, n0=0):
+    def __init__(self, grid: api.Grid, ux0, uy0, p0, nsteps: int, prec="f32", seg=None, n0=0, keep_all=False):
         self.g, self.ux0, self.uy0, self.p0 = grid, ux0, uy0, p0
         self.n = int(nsteps)
         self.prec = prec
         self.n0 = int(n0)
+        self.keep_all = bool(keep_all)
         self.seg = int(seg) if seg else max(1, int(round(math.sqrt(max(self.n, 1)))))
 
     # ------------------------------------------------------------ forward
@@ -36,6 +41,15 @@ class Rollout:
         """rho_N (ny, nx); if `checkpoints` is a list, the states f^(k seg) are appended to it."""
         g = self.g
         cur = self._init(rho0)
+        if checkpoints is not None and self.keep_all and self.n > 0:
+            # every state f^1 .. f^N recorded (two steps per pass); the list gets f^0 .. f^(N-1).
+            # One allocation for all of them (a state's size is a multiple of 256 bytes, so
+            # every view stays aligned): N separate allocations cost ~18 us each on the host.
+            dt = api.DTYPE[api._prec(self.prec)]
+            outs = list(torch.empty((self.n, 9, g.ny, g.pitch), dtype=dt, device=cur.device).unbind(0))
+            api.run_record(g, cur, outs, n0=self.n0, prec=self.prec)
+            checkpoints.extend([cur] + outs[:-1])
+            return api.moments(g, outs[-1], prec=self.prec, flags=False)[0]
         nxt = api.empty(g, self.prec, cur.device)
         done = 0
         while done < self.n:
@@ -61,6 +75,9 @@ class Rollout:
         gbuf[:, :, :g.nx] = g_rhoN.to(torch.float64).unsqueeze(0)
         gtmp = api.empty(g, "f64", dev)
         gtmp.zero_()
+        if self.keep_all and self.n > 0:   # checkpoints holds every state f^0 .. f^(N-1)
+            res = api.adjoint_run(g, checkpoints, gbuf, gtmp, n0=self.n0, prec=self.prec)
+            return api.init_adjoint(g, rho0.detach().to(torch.float64).contiguous(), self.ux0, self.uy0, self.p0, res)
         nseg = len(checkpoints)
         states = [None] * self.seg
         for s in reversed(range(nseg)):

@@ -91,12 +91,12 @@ def _dmr_problem(nx, ny, steps):
     return cfg, fields, target
 
 
-def _gpu_gradient(cfg, fields, target_rho, prec, seg=None):
+def _gpu_gradient(cfg, fields, target_rho, prec, seg=None, keep_all=False):
     lb = _lb()
     from paper_0706_0405_amd import rollout
     g = lb.Grid.from_workload(cfg)
     rho, ux, uy, p = [torch.tensor(np.ascontiguousarray(a), dtype=F64, device=DEV) for a in fields]
-    R = rollout.Rollout(g, ux, uy, p, cfg["steps"], prec=prec, seg=seg)
+    R = rollout.Rollout(g, ux, uy, p, cfg["steps"], prec=prec, seg=seg, keep_all=keep_all)
     tgt = R.forward_density(torch.tensor(target_rho, dtype=F64, device=DEV))
     loss, grad = R.loss_and_grad(rho, tgt)
     return R, loss, grad, tgt
@@ -126,6 +126,17 @@ def test_checkpoint_interval_does_not_change_the_gradient():
     cfg, fields, target = _dmr_problem(64, 16, 50)
     grads = [_gpu_gradient(cfg, fields, target, "f64", seg=s)[2] for s in (1, 7, 50)]
     assert torch.equal(grads[0], grads[1]) and torch.equal(grads[0], grads[2])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_keeping_every_state_gives_the_same_gradient(prec):
+    """keep_all: every state recorded during the forward (two steps per pass), no
+    recomputation; bitwise the gradient of the checkpointed sweep, odd step count."""
+    cfg, fields, target = _dmr_problem(64, 16, 51)
+    ref = _gpu_gradient(cfg, fields, target, prec, seg=7)[2]
+    got = _gpu_gradient(cfg, fields, target, prec, keep_all=True)[2]
+    assert torch.isfinite(ref).all()
+    assert torch.equal(got, ref)
 
 
 def test_rollout_gradient_central_differences_on_full_grid():
