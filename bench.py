@@ -244,14 +244,14 @@ def bench_adjoint_step(dev, fwd_ms, nsteps=20):
             "finite": finite}
 
 
-def bench_vn(dev, alphas=(0.025, 0.05, 0.075, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0.4, 0.45, 0.5), nkx=64):
-    """GPU von Neumann chooser on the 256 batched Riemann problems: for each problem's
-    left, right and two star states, the largest stable alpha = dt c2 / dx among the
-    candidates over 64 x 4 wave vectors of its periodic grid, the problem taking the
-    minimum over its states; the scan rate vs the oracle's eigenvalues on the host."""
+VN_ALPHAS = (0.025, 0.05, 0.075, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0.4, 0.45, 0.5)
+
+
+def vn_cases(alphas=VN_ALPHAS, nkx=64):
+    """The scanner's inputs for the 256 batched Riemann problems: for each problem's
+    left, right and two star states a case, its candidate time steps (alpha dx / c2)
+    and its problem index, and the 64 x 4 wave vectors of a 4-row periodic grid."""
     import math as m
-    import torch
-    from oracle import vonneumann as ovn
     from paper_0706_0405_amd import vn
     import paper_0706_0405_amd as lb
     from workloads import gasdyn, problems as P
@@ -267,9 +267,23 @@ def bench_vn(dev, alphas=(0.025, 0.05, 0.075, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0
             cases.append(vn.case(g, s))
             dts.append([a * g.dx / g.c2 for a in alphas])
             owner.append(k)
-    kx = torch.arange(nkx, dtype=torch.float64, device=dev) * (2 * m.pi / nkx)
-    kx = kx.repeat_interleave(4).contiguous()
-    ky = (torch.arange(4, dtype=torch.float64, device=dev) * (m.pi / 2)).repeat(nkx).contiguous()
+    kx = [k * (2 * m.pi / nkx) for k in range(nkx) for _ in range(4)]
+    ky = [j * (m.pi / 2) for _ in range(nkx) for j in range(4)]
+    return cfgs, cases, dts, owner, kx, ky
+
+
+def bench_vn(dev, alphas=VN_ALPHAS, nkx=64):
+    """GPU von Neumann chooser on the 256 batched Riemann problems: for each problem's
+    left, right and two star states, the largest stable alpha = dt c2 / dx among the
+    candidates over 64 x 4 wave vectors of its periodic grid, the problem taking the
+    minimum over its states."""
+    import math as m
+    import torch
+    from paper_0706_0405_amd import vn
+
+    cfgs, cases, dts, owner, kxl, kyl = vn_cases(alphas, nkx)
+    kx = torch.tensor(kxl, dtype=torch.float64, device=dev)
+    ky = torch.tensor(kyl, dtype=torch.float64, device=dev)
     vn.max_stable_dt(cases, dts, kx, ky, 1e-9)        # warm (module load, first launch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -287,22 +301,8 @@ def bench_vn(dev, alphas=(0.025, 0.05, 0.075, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0
             per[k] = min(per.get(k, a), a)
         v = sorted(per.values())
         return {"min": v[0], "median": v[len(v) // 2], "max": v[-1], "at_least_0.1": sum(a >= 0.1 for a in v)}
-    # the oracle on a bounded host sample of the same points
-    sample = [(c, k) for c in range(0, len(cases), 97) for k in range(0, kx.numel(), 37)]
-    t0 = time.perf_counter()
-    js = {}
-    for c, q in sample:
-        cc = cases[c]
-        prm = {"c1": cc.c1, "c2": cc.c2, "eta0": cc.eta0, "gamma": cc.gamma, "tau": cc.tau, "beta": cc.beta,
-               "dt": dts[c][0], "dx": cc.dx, "lam": [cc.lam[i] for i in range(9)]}
-        stt = (cc.rho, cc.ux, cc.uy, cc.T)
-        if c not in js:
-            js[c] = ovn.collision_jacobian(*stt, cc.c1, cc.c2, cc.eta0, cc.gamma)
-        ovn.max_modulus(stt, prm, float(kx[q]), float(ky[q]), js[c])
-    t_cpu = time.perf_counter() - t0
     return {"problems": len(cfgs), "states_per_problem": 4, "alphas": list(alphas), "wave_vectors": kx.numel(),
             "points": points, "ms": t * 1e3, "points_per_s": points / t,
-            "cpu_oracle_points_per_s": len(sample) / t_cpu, "cpu_oracle_sample_points": len(sample),
             "chosen_alpha_strict": per_problem(best), "tol_run": tol_run,
             "chosen_alpha_growth_2x_over_run": per_problem(best_run)}
 
@@ -432,13 +432,31 @@ def cpu_baseline(target_s=15.0):
         scheme.run(q, scheme.init(q, *P.init_fields(c)), 4, 1)
         sites += q.nx * q.ny
     tb = time.perf_counter() - t0
+    # the von Neumann scan: the oracle's amplification-matrix modulus on a sample of the
+    # scanner's points (every 97th case, every 37th wave vector, the first candidate step)
+    from oracle import vonneumann as ovn
+    _, cases, dts, _, kx, ky = vn_cases()
+    vsample = [(c, q) for c in range(0, len(cases), 97) for q in range(0, len(kx), 37)]
+    t0 = time.perf_counter()
+    js = {}
+    for c, q in vsample:
+        cc = cases[c]
+        prm = {"c1": cc.c1, "c2": cc.c2, "eta0": cc.eta0, "gamma": cc.gamma, "tau": cc.tau, "beta": cc.beta,
+               "dt": dts[c][0], "dx": cc.dx, "lam": [cc.lam[i] for i in range(9)]}
+        stt = (cc.rho, cc.ux, cc.uy, cc.T)
+        if c not in js:
+            js[c] = ovn.collision_jacobian(*stt, cc.c1, cc.c2, cc.eta0, cc.gamma)
+        ovn.max_modulus(stt, prm, kx[q], ky[q], js[c])
+    tv = time.perf_counter() - t0
     return {"value": pb.nx * pb.ny * n / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
             "kind": "oracle", "host_cpu": model, "host_threads": os.cpu_count(),
             "sample": "FP64 oracle, %d steps of the same double-Mach problem at the same spacing on a "
                       "%dx%d grid (%.1f s)" % (n, pb.nx, pb.ny, dt),
             "configs": configs,
             "batched": {"problems": len(bcfgs), "steps_each": 4, "s": tb, "mlups": sites * 4 / tb / 1e6,
-                        "sample": "the 256 batched problems one after the other in this process"}}
+                        "sample": "the 256 batched problems one after the other in this process"},
+            "vn_scan": {"points": len(vsample), "s": tv, "points_per_s": len(vsample) / tv,
+                        "sample": "every 97th state case, every 37th wave vector, first candidate time step"}}
 
 
 def main():
