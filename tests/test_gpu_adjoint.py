@@ -48,6 +48,35 @@ def test_step_adjoint_matches_oracle_vjp(bcs, size):
     assert err < 1e-13
 
 
+def test_roofline_grid_adjoint_sampled_rows():
+    """One adjoint step on the 8192 x 2048 benchmark grid, as the benchmark launches it
+    (default tiles), in both storage precisions of f. g^{n+1} is nonzero only on the
+    rows next to the sampled ones, so the sampled rows of g^n are exact; against
+    autograd through the oracle's step of those rows (f as stored)."""
+    lb = _lb()
+    cfg = P.roofline_grid()
+    g = lb.Grid.from_workload(cfg)
+    pb = scheme.Problem.from_dict(cfg)
+    rows = [0, 1, 31, 32, 1023, 1024, 2047]
+    win = sorted({min(max(r + d, 0), g.ny - 1) for r in rows for d in (-1, 0, 1)})
+    raw = P.random_distributions(g.nx, g.ny, seed=41)
+    wt = torch.tensor(np.random.default_rng(42).standard_normal((9, len(win), g.nx)), dtype=F64)
+    G = torch.zeros(9, g.ny, g.nx, dtype=F64)
+    G[:, win] = wt
+    for prec in ("f64", "f32"):
+        say("case roofline adjoint", prec)
+        f0 = torch.tensor(raw, dtype=torch.float64 if prec == "f64" else torch.float32).to(F64)
+        f = f0.clone().requires_grad_(True)
+        (scheme.step_rows(pb, f, 5, win) * wt).sum().backward()
+        want = f.grad[:, rows]
+        got = lb.step_adjoint(g, _put(lb, g, f0, prec), _put(lb, g, G), n=5, prec=prec)
+        got = got[:, rows, :g.nx].cpu()
+        torch.cuda.empty_cache()
+        err = float((got - want).abs().max() / want.abs().max())
+        say("roofline adjoint", prec, "err", err)
+        assert err < 1e-13
+
+
 def test_init_adjoint_matches_oracle():
     lb = _lb()
     cfg = P.double_mach(nx=48, ny=12)
