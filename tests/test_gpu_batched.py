@@ -109,11 +109,13 @@ def test_graph_replays_continue_the_run():
 
 
 def test_batched_against_oracle_fp32_bound():
-    """The shortest problems of the 256-problem draw, 2000 steps, against the FP64 oracle
-    (rows of a y-uniform problem are identical, so the oracle runs one row)."""
+    """The shortest problems of the 256-problem draw, two of the fast subset and the
+    longest, 2000 steps, against the FP64 oracle (rows of a y-uniform problem are
+    identical, so the oracle runs one row)."""
     cfgs, rej = P.batched(nprob=256, seed=0, steps=2000)
     order = sorted(range(len(cfgs)), key=lambda k: cfgs[k]["nx"])
     pick = order[:4] + [k for k in range(7, 256, 8) if cfgs[k]["nx"] < 400][:2]   # include the fast subset
+    pick.append(order[-1])   # and the longest problem (many interior strips)
     sub = [cfgs[k] for k in pick]
     lb, grids, B, fa, fb, s = _make(sub)
     with torch.cuda.stream(s):
