@@ -984,9 +984,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     KTConsts K, const S* __restrict__ fin, S* __restrict__ fout, S* __restrict__ f1out, int rows, int nstrips,
     int ntiles, int xcd_map, int ish_lo, int ish_hi, int ish2_lo, int ish2_hi) {
   static_assert(!(WIDE && REC), "recording runs on arrays below 4 GiB");
-  // stores: non-temporal for double, ordinary for float storage (float: 0.164
-  // vs 0.168-0.174 ms per step on the 8192 x 2048 grid on two devices; double:
-  // equal)
+  // stores: non-temporal for double, ordinary for float storage (8192 x 2048
+  // grid, ms per step: float 0.164 vs 0.168-0.174 with non-temporal stores, on
+  // two devices; double 0.2650 vs 0.2697 with ordinary stores, three runs each)
   constexpr int AUX = sizeof(S) == 8 ? 2 : 0;
   const View<S, AUX> fi0 = make_view<S, AUX>(K, fin), fo0 = make_view<S, AUX>(K, fout);
   const int lane = threadIdx.x & 63;
