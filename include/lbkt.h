@@ -53,7 +53,8 @@
  *   - Parameter, size and alias errors are detected on the host before any
  *     launch and return a negative lb_status; lb_last_error() gives detail
  *     text (thread-local). HIP errors map to LB_EHIP.
- *   - Numerical blow-up is reported through lb_moments' flags.
+ *   - Numerical blow-up is asynchronous: lb_moments records it in a device flags
+ *     word, and lb_check_flags turns that word into LB_ENONFINITE.
  */
 #ifndef LBKT_H
 #define LBKT_H
@@ -69,7 +70,7 @@ typedef enum {
   LB_EINVAL = -1,      /* null pointer, bad size, pitch or alignment */
   LB_EPARAM = -2,      /* c1 == c2, c1,c2,eta0,dx,dt,tau <= 0, beta outside [0,0.5], gamma <= 1, lambda < 0 */
   LB_EALIAS = -3,      /* input and output arrays overlap */
-  LB_ENONFINITE = -4,  /* reserved for callers that turn flags into a status */
+  LB_ENONFINITE = -4,  /* lb_check_flags: some site was non-finite or had rho <= 0 */
   LB_EHIP = -5,        /* a HIP runtime call failed */
   LB_ENOMEM = -6,      /* internal metadata allocation failed */
   LB_EUNSUPPORTED = -7 /* valid request the library does not implement */
@@ -169,9 +170,23 @@ lb_status lb_run(const lb_grid* grid, lb_prec prec, void* f_a, void* f_b, int64_
 lb_status lb_moments(const lb_grid* grid, lb_prec prec, const void* f, double* rho, double* ux,
                      double* uy, double* T, uint32_t* flags, void* stream);
 
-/* Domain totals (sum over sites of rho, rho ux, rho uy, rho (b T + u^2)) into a
- * device double[4]. Deterministic (fixed reduction order). Uses an internal
- * per-device workspace allocated on first use. */
+/* Blow-up as a status (Sec. 3: outside its linear-stability range the scheme
+ * grows without bound; a finite f^eq needs rho != 0, Eq. (e16) divides by it).
+ * flags: the device uint32[4] that lb_moments filled (its work must be on
+ * `stream` or finished). Waits for `stream` (synchronous), copies the four words
+ * to host_flags (host uint32[4], may be NULL) and returns LB_ENONFINITE when
+ * flags[0] has LB_FLAG_NONFINITE or LB_FLAG_RHO_NONPOS (lb_last_error gives the
+ * counts), LB_OK otherwise. T <= 0 alone is not an error: f^eq is a polynomial
+ * in T. LB_EINVAL for flags == NULL, LB_EHIP if the copy fails. */
+lb_status lb_check_flags(const uint32_t* flags, uint32_t* host_flags, void* stream);
+
+/* Domain totals of the collision invariants into a device double[4]: the sums
+ * over sites of rho = sum_i f_i (Eq. (e4)), rho ux and rho uy = sum_i f_i v_i
+ * (Eq. (e5)) and rho (b T + u^2) = sum_i f_i (v_i^2 + eta_i^2) (Eq. (e7)).
+ * Deterministic (fixed reduction order). Uses a per-device workspace allocated
+ * on first use (and grown when a larger grid needs more partial sums); calls on
+ * different streams are ordered on it (each waits for the previous call's
+ * kernels before writing it). */
 lb_status lb_invariants(const lb_grid* grid, lb_prec prec, const void* f, double* out4,
                         void* stream);
 

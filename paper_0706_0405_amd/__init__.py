@@ -7,5 +7,5 @@ runs in hand-written HIP kernels (liblbkt.so, C ABI in include/lbkt.h); this
 package is the thin Python binding over torch device tensors.
 """
 from . import _lib  # noqa: F401
-from .api import (Batch, Grid, autotune, empty, init, init_adjoint, interior, invariants, moments,  # noqa: F401
+from .api import (Batch, Grid, autotune, check_flags, empty, init, init_adjoint, interior, invariants, moments,  # noqa: F401
                   run, step, step_adjoint, validate)

@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBKT_LIB") or os.path.join(HERE, "liblbkt.so")
 
 LB_F64, LB_F32 = 0, 1
+LB_ENONFINITE = -4
 BC = {"periodic": 0, "outflow": 1, "wall": 2, "inflow": 3, "shock": 4}
 FLAG_NONFINITE, FLAG_RHO_NONPOS, FLAG_T_NONPOS = 1, 2, 4
 
@@ -59,6 +60,7 @@ _SIGS = {
                          POINTER(LbTile), c_void_p]),
     "lb_moments": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                              c_void_p, c_void_p]),
+    "lb_check_flags": (c_int32, [c_void_p, POINTER(c_uint32), c_void_p]),
     "lb_invariants": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, c_void_p, c_void_p]),
     "lb_step_adjoint": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
     "lb_run_record": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, POINTER(c_void_p), c_int64, c_int32,

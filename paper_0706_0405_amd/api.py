@@ -157,18 +157,33 @@ def run(grid: Grid, f_a, f_b, nsteps, n0=0, prec="f64", use_graph=False, tile=No
     return f_a if nsteps % 2 == 0 else f_b
 
 
-def moments(grid: Grid, f, prec="f64", flags=True):
-    """(rho, ux, uy, T[, flags]) as (ny, nx) float64 tensors; flags = int64 tensor (4,)."""
+def moments(grid: Grid, f, prec="f64", flags=True, check_finite=False):
+    """(rho, ux, uy, T[, flags]) as (ny, nx) float64 tensors; flags = int64 tensor (4,).
+    check_finite: wait for the result and raise LbError (LB_ENONFINITE) if some site
+    is non-finite or has rho <= 0 (lb_check_flags)."""
     pr = _prec(prec)
     _check_f(grid, pr, f, "f")
     dev = f.device
     outs = [torch.empty((grid.ny, grid.nx), dtype=torch.float64, device=dev) for _ in range(4)]
-    fl = torch.empty(4, dtype=torch.int32, device=dev) if flags else None
+    fl = torch.empty(4, dtype=torch.int32, device=dev) if (flags or check_finite) else None
     check(lib().lb_moments(ctypes.byref(grid.c()), pr, _ptr(f), *[_ptr(o) for o in outs], _ptr(fl),
                            _stream(dev)))
+    if check_finite:
+        check_flags(fl)
     if flags:
         return (*outs, fl.to(torch.int64) & 0xFFFFFFFF)
     return tuple(outs)
+
+
+def check_flags(flags):
+    """Raise LbError (LB_ENONFINITE) when the raw device flags word that lb_moments
+    wrote (an int32 tensor of 4) reports a non-finite site or rho <= 0; returns the
+    four words as Python ints otherwise (lb_check_flags, synchronous)."""
+    if flags.dtype != torch.int32 or flags.numel() != 4 or flags.device.type != "cuda":
+        raise ValueError("flags must be the int32 device tensor of 4 words that lb_moments filled")
+    host = (ctypes.c_uint32 * 4)()
+    check(lib().lb_check_flags(_ptr(flags), host, _stream(flags.device)))
+    return list(host)
 
 
 def invariants(grid: Grid, f, prec="f64"):

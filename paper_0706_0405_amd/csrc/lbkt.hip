@@ -1672,13 +1672,32 @@ extern "C" lb_status lb_step(const lb_grid* g, lb_prec prec, const void* fin, vo
 }
 
 namespace {
+// A captured step loop and an event recorded after its latest launch: an exec is
+// destroyed only once that event has completed (a replay may still run on any
+// stream when the cache evicts it).
 struct GraphEntry {
   std::string key;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
 };
 std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;  // small LRU of captured step loops
 }  // namespace
+
+// Wait for the latest launch of exec (event `done`), then destroy both.
+static void destroy_exec(hipGraphExec_t exec, hipEvent_t done) {
+  if (done) {
+    (void)hipEventSynchronize(done);
+    (void)hipEventDestroy(done);
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+}
+
+static lb_status launch_exec(hipGraphExec_t exec, hipEvent_t done, hipStream_t st) {
+  HIP_CHECK(hipGraphLaunch(exec, st));
+  HIP_CHECK(hipEventRecord(done, st));
+  return LB_OK;
+}
 
 static std::string run_key(const lb_grid* g, lb_prec prec, const void* fa, const void* fb, int64_t step0,
                            int nsteps, int bx, int rows, void* stream) {
@@ -1709,10 +1728,7 @@ extern "C" lb_status lb_run(const lb_grid* g, lb_prec prec, void* fa, void* fb, 
       run_key(g, prec, fa, fb, step0, nsteps, t.bx, (t.rows * 1000003 + t.blocks) * 3 + t.steps, stream);
   std::lock_guard<std::mutex> lock(g_graph_mu);
   for (auto& e : g_graphs)
-    if (e.key == key) {
-      HIP_CHECK(hipGraphLaunch(e.exec, st));
-      return LB_OK;
-    }
+    if (e.key == key) return launch_exec(e.exec, e.done, st);
   HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   const lb_status ls = launch_steps(g, K, prec, fa, fb, step0, nsteps, t, st);
   hipGraph_t graph = nullptr;
@@ -1726,13 +1742,18 @@ extern "C" lb_status lb_run(const lb_grid* g, lb_prec prec, void* fa, void* fb, 
   hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (ie != hipSuccess) return fail(LB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+  hipEvent_t done = nullptr;
+  const hipError_t ee = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+  if (ee != hipSuccess) {
+    (void)hipGraphExecDestroy(exec);
+    return fail(LB_EHIP, std::string("hipEventCreateWithFlags: ") + hipGetErrorString(ee));
+  }
   if (g_graphs.size() >= 8) {
-    (void)hipGraphExecDestroy(g_graphs.front().exec);
+    destroy_exec(g_graphs.front().exec, g_graphs.front().done);
     g_graphs.erase(g_graphs.begin());
   }
-  g_graphs.push_back({key, exec});
-  HIP_CHECK(hipGraphLaunch(exec, st));
-  return LB_OK;
+  g_graphs.push_back({key, exec, done});
+  return launch_exec(exec, done, st);
 }
 
 extern "C" lb_status lb_moments(const lb_grid* g, lb_prec prec, const void* f, double* rho, double* ux,
@@ -1755,30 +1776,56 @@ extern "C" lb_status lb_moments(const lb_grid* g, lb_prec prec, const void* f, d
   return LB_OK;
 }
 
+extern "C" lb_status lb_check_flags(const uint32_t* flags, uint32_t* host_flags, void* stream) {
+  if (!flags) return fail(LB_EINVAL, "flags is NULL");
+  uint32_t h[4] = {0u, 0u, 0u, 0u};
+  hipStream_t st = (hipStream_t)stream;
+  HIP_CHECK(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  if (host_flags) std::memcpy(host_flags, h, sizeof(h));
+  if (h[0] & (LB_FLAG_NONFINITE | LB_FLAG_RHO_NONPOS)) {
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "blow-up: %u non-finite sites, %u sites with rho <= 0 (%u with T <= 0)", h[1],
+                  h[2], h[3]);
+    return fail(LB_ENONFINITE, buf);
+  }
+  return LB_OK;
+}
+
+// Partition of lb_invariants: nb blocks of rpb rows each (nb <= INV_MAX_PARTS).
+static constexpr int INV_MAX_PARTS = 4096;
+
+static void inv_partition(const lb_grid* g, int* rpb, int* nb) {
+  const int nblk = std::min(g->ny, INV_MAX_PARTS);
+  *rpb = (g->ny + nblk - 1) / nblk;
+  *nb = (g->ny + *rpb - 1) / *rpb;
+}
+
+// The two kernels of lb_invariants over a partial-sum buffer of nb * 4 doubles.
+static lb_status launch_invariants(const KTConsts& K, lb_prec prec, const void* f, int rpb, int nb, double* part,
+                                   double* out4, hipStream_t st) {
+  if (prec == LB_F64)
+    hipLaunchKernelGGL(k_inv_partial<double>, dim3(nb), dim3(256), 0, st, K, (const double*)f, rpb, part);
+  else
+    hipLaunchKernelGGL(k_inv_partial<float>, dim3(nb), dim3(256), 0, st, K, (const float*)f, rpb, part);
+  HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_inv_final, dim3(1), dim3(256), 0, st, (const double*)part, nb, out4);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
 namespace {
+// Per-device workspace of lb_invariants and an event recorded after the last
+// kernel that read it: the next call, on whatever stream, waits for that event
+// before its kernels write the buffer, and a buffer is freed only after it.
 struct Workspace {
   void* ptr = nullptr;
   size_t bytes = 0;
+  hipEvent_t last = nullptr;
 };
 std::mutex g_ws_mu;
 std::map<int, Workspace> g_ws;
 }  // namespace
-
-static lb_status workspace(size_t bytes, void** out) {
-  int dev = 0;
-  HIP_CHECK(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lock(g_ws_mu);
-  Workspace& w = g_ws[dev];
-  if (w.bytes < bytes) {
-    if (w.ptr) HIP_CHECK(hipFree(w.ptr));
-    w.ptr = nullptr;
-    w.bytes = 0;
-    if (hipMalloc(&w.ptr, bytes) != hipSuccess) return fail(LB_ENOMEM, "workspace allocation failed");
-    w.bytes = bytes;
-  }
-  *out = w.ptr;
-  return LB_OK;
-}
 
 extern "C" lb_status lb_invariants(const lb_grid* g, lb_prec prec, const void* f, double* out4, void* stream) {
   lb_status s;
@@ -1786,19 +1833,31 @@ extern "C" lb_status lb_invariants(const lb_grid* g, lb_prec prec, const void* f
   if (!out4) return fail(LB_EINVAL, "out4 is NULL");
   KTConsts K;
   build_consts(g, &K);
-  const int nblk = std::min(g->ny, 4096);
-  const int rpb = (g->ny + nblk - 1) / nblk;
-  const int nb = (g->ny + rpb - 1) / rpb;
-  void* part = nullptr;
-  if ((s = workspace((size_t)nb * 4 * sizeof(double), &part))) return s;
+  int rpb, nb;
+  inv_partition(g, &rpb, &nb);
+  const size_t bytes = (size_t)nb * 4 * sizeof(double);
   hipStream_t st = (hipStream_t)stream;
-  if (prec == LB_F64)
-    hipLaunchKernelGGL(k_inv_partial<double>, dim3(nb), dim3(256), 0, st, K, (const double*)f, rpb, (double*)part);
-  else
-    hipLaunchKernelGGL(k_inv_partial<float>, dim3(nb), dim3(256), 0, st, K, (const float*)f, rpb, (double*)part);
-  HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_inv_final, dim3(1), dim3(256), 0, st, (const double*)part, nb, out4);
-  HIP_CHECK(hipGetLastError());
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  // the whole enqueue under the lock, so that calls from several threads order
+  // their use of the buffer as they take the lock
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  Workspace& w = g_ws[dev];
+  if (!w.last) HIP_CHECK(hipEventCreateWithFlags(&w.last, hipEventDisableTiming));
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      HIP_CHECK(hipEventSynchronize(w.last));   // the previous call's kernels are done with it
+      HIP_CHECK(hipFree(w.ptr));
+    }
+    w.ptr = nullptr;
+    w.bytes = 0;
+    if (hipMalloc(&w.ptr, bytes) != hipSuccess) return fail(LB_ENOMEM, "workspace allocation failed");
+    w.bytes = bytes;
+  } else {
+    HIP_CHECK(hipStreamWaitEvent(st, w.last, 0));
+  }
+  if ((s = launch_invariants(K, prec, f, rpb, nb, (double*)w.ptr, out4, st))) return s;
+  HIP_CHECK(hipEventRecord(w.last, st));
   return LB_OK;
 }
 
@@ -1940,6 +1999,7 @@ struct lb_batch {
   int g_bx = 0;
   int g_steps = 0;
   void* g_stream = nullptr;
+  hipEvent_t done = nullptr;   // recorded after each replay (the exec is destroyed after it)
 };
 
 static lb_status batch_items(lb_batch* b) {
@@ -2127,9 +2187,13 @@ extern "C" lb_status lb_step_batched(lb_batch* b, void* fa, void* fb, int32_t ns
     b->step += nsteps;
     return LB_OK;
   }
+  if (!b->done) HIP_CHECK(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
   if (!(b->exec && b->g_fa == fa && b->g_fb == fb && b->g_nsteps == nsteps && b->g_bx == b->block_x &&
         b->g_steps == b->steps && b->g_stream == stream)) {
-    if (b->exec) HIP_CHECK(hipGraphExecDestroy(b->exec));
+    if (b->exec) {
+      HIP_CHECK(hipEventSynchronize(b->done));   // its last replay may still run, on any stream
+      HIP_CHECK(hipGraphExecDestroy(b->exec));
+    }
     b->exec = nullptr;
     HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     const lb_status ls = batched_steps(b, fa, fb, nsteps, st);
@@ -2151,12 +2215,17 @@ extern "C" lb_status lb_step_batched(lb_batch* b, void* fa, void* fb, int32_t ns
     b->g_stream = stream;
   }
   HIP_CHECK(hipGraphLaunch(b->exec, st));
+  HIP_CHECK(hipEventRecord(b->done, st));
   b->step += nsteps;
   return LB_OK;
 }
 
 extern "C" void lb_batch_destroy(lb_batch* b) {
   if (!b) return;
+  if (b->done) {
+    (void)hipEventSynchronize(b->done);
+    (void)hipEventDestroy(b->done);
+  }
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->d_consts) (void)hipFree(b->d_consts);
   if (b->d_info) (void)hipFree(b->d_info);

@@ -136,6 +136,7 @@ def test_alias_and_alignment_rejected_before_launch():
     st = L.lb_step(ctypes.byref(g), 7, buf, ctypes.c_void_p(1 << 30), 0, None)
     assert st == -1
     assert L.lb_status_str(-4) == b"LB_ENONFINITE"
+    assert L.lb_check_flags(None, None, None) == -1 and b"NULL" in L.lb_last_error()
 
 
 def test_run_record_arguments_rejected_before_launch():

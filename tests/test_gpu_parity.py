@@ -229,6 +229,49 @@ def test_flags_report_nonfinite_and_nonpositive():
     assert fl[1] == 2 and fl[2] == 1 and fl[3] == 1, fl
 
 
+def test_blow_up_surfaces_as_lb_enonfinite():
+    """lb_check_flags turns the flags word into a status: LB_ENONFINITE for a
+    non-finite site or rho <= 0 (with the counts in the message), LB_OK for a clean
+    field and for T <= 0 alone."""
+    from paper_0706_0405_amd import _lib
+    lb = _lb()
+    cfg = P.periodic_smooth(nx=100, ny=10)
+    g, f = gpu_run(cfg, 6, "f64")
+    _, _, _, _, flags = lb.moments(g, f, check_finite=True)    # clean: no exception
+    assert int(flags[0]) == 0
+    t = f.clone()
+    t[:, 7, 12] = 0.0
+    t[3, 7, 12] = 1.0                    # T = 0 only: not an error
+    _, _, _, _, flags = lb.moments(g, t, check_finite=True)
+    assert int(flags[0]) == 4
+    for site in ((2, 5), (4, 9)):
+        t = f.clone()
+        if site == (2, 5):
+            t[0, 2, 5] = float("nan")
+        else:
+            t[:, 4, 9] = -1.0            # rho < 0
+        with pytest.raises(_lib.LbError) as ei:
+            lb.moments(g, t, check_finite=True)
+        assert ei.value.status == _lib.LB_ENONFINITE, ei.value
+        assert ("1 non-finite" in str(ei.value)) == (site == (2, 5)), str(ei.value)
+    # a run that blows up: Fig. 5's eta0 = 5 at alpha = 0.3 and u = (10, 0), T = 1 is
+    # linearly unstable (spectral radius 1.52 on this grid): a 1e-10 density
+    # perturbation reaches O(1) after about 55 steps, and 400 steps leave sites with
+    # rho <= 0 or non-finite values
+    from oracle import vonneumann as ovn
+    p = ovn.figure_params(alpha=0.3, eta0=5.0)
+    g2 = lb.Grid(nx=60, ny=4, dx=p["dx"], dt=p["dt"], c1=p["c1"], c2=p["c2"], eta0=p["eta0"], gamma=p["gamma"],
+                 tau=p["tau"], beta=p["beta"], lam=list(p["lam"]), edges=[{"kind": "periodic"}] * 4)
+    xi = np.random.default_rng(4).uniform(-1.0, 1.0, size=(4, 60))
+    rho = torch.tensor(1.0 + 1e-10 * xi, dtype=F64, device=DEV)
+    fa = lb.init(g2, rho, torch.full_like(rho, 10.0), torch.zeros_like(rho), rho.clone())
+    out = lb.run(g2, fa, lb.empty(g2, "f64", DEV), 400)
+    with pytest.raises(_lib.LbError) as ei:
+        lb.moments(g2, out, check_finite=True)
+    say("blow-up status:", ei.value)
+    assert ei.value.status == _lib.LB_ENONFINITE
+
+
 # ------------------------------------------------------------------ full size, bench launch shape
 
 def test_roofline_grid_one_step_sampled_rows():
