@@ -190,6 +190,21 @@ lb_status lb_check_flags(const uint32_t* flags, uint32_t* host_flags, void* stre
 lb_status lb_invariants(const lb_grid* grid, lb_prec prec, const void* f, double* out4,
                         void* stream);
 
+/* lb_invariants for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results (bitwise), with the partial sums in a fixed array of the
+ * library instead of a workspace: 4096 records of 4 doubles (128 KiB) per
+ * device, set up on the first call on a device and held until the process ends.
+ * Calls no hipMalloc, hipFree or other allocating routine. Every call on a
+ * device shares that device's array, and the array keeps the last call's
+ * partial sums (each call writes every record it reads, so nothing needs
+ * clearing): calls that overlap on one device (on different streams or host
+ * threads) race on it. LB_EINVAL if the grid needs more than 4096 partial
+ * records (the partition never does: it caps the number of row blocks at 4096),
+ * and the argument errors of lb_invariants. */
+lb_status lb_invariants_noalloc(const lb_grid* grid, lb_prec prec, const void* f, double* out4,
+                                void* stream);
+
 /* Adjoint (vector-Jacobian product) of lb_step at f_n: g_n = (dS/df)^T g_np1.
  * g_np1 and g_n are float64 arrays of the distribution layout; f_n has the
  * storage type of `prec` (the float32 rounding of the store is treated as the

@@ -62,6 +62,7 @@ _SIGS = {
                              c_void_p, c_void_p]),
     "lb_check_flags": (c_int32, [c_void_p, POINTER(c_uint32), c_void_p]),
     "lb_invariants": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, c_void_p, c_void_p]),
+    "lb_invariants_noalloc": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, c_void_p, c_void_p]),
     "lb_step_adjoint": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
     "lb_run_record": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, POINTER(c_void_p), c_int64, c_int32,
                                 c_void_p]),

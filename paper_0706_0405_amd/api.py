@@ -186,12 +186,17 @@ def check_flags(flags):
     return list(host)
 
 
-def invariants(grid: Grid, f, prec="f64"):
-    """(4,) float64 device tensor: totals of rho, rho ux, rho uy, rho (b T + u^2)."""
+def invariants(grid: Grid, f, prec="f64", out=None, noalloc=False):
+    """(4,) float64 device tensor: totals of rho, rho ux, rho uy, rho (b T + u^2).
+    noalloc: lb_invariants_noalloc (the library's fixed array instead of a workspace)."""
     pr = _prec(prec)
     _check_f(grid, pr, f, "f")
-    out = torch.empty(4, dtype=torch.float64, device=f.device)
-    check(lib().lb_invariants(ctypes.byref(grid.c()), pr, _ptr(f), _ptr(out), _stream(f.device)))
+    if out is None:
+        out = torch.empty(4, dtype=torch.float64, device=f.device)
+    if out.dtype != torch.float64 or out.numel() != 4 or not out.is_contiguous() or out.device.type != "cuda":
+        raise ValueError("out must be a contiguous float64 GPU tensor of 4 elements")
+    fn = lib().lb_invariants_noalloc if noalloc else lib().lb_invariants
+    check(fn(ctypes.byref(grid.c()), pr, _ptr(f), _ptr(out), _stream(f.device)))
     return out
 
 

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbkt.so")
-SOURCES = [os.path.join(HERE, "csrc", "lbkt.hip"), os.path.join(HERE, "csrc", "vn.hip")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("lbkt.hip", "vn.hip", "noalloc.hip")]
 DEPS = SOURCES + [os.path.join(HERE, "csrc", "kt_site.hpp"), os.path.join(HERE, "csrc", "lbkt_internal.hpp"),
                   os.path.join(ROOT, "include", "lbkt.h")]
 

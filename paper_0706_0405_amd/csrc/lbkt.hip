@@ -1792,18 +1792,24 @@ extern "C" lb_status lb_check_flags(const uint32_t* flags, uint32_t* host_flags,
   return LB_OK;
 }
 
-// Partition of lb_invariants: nb blocks of rpb rows each (nb <= INV_MAX_PARTS).
-static constexpr int INV_MAX_PARTS = 4096;
-
-static void inv_partition(const lb_grid* g, int* rpb, int* nb) {
-  const int nblk = std::min(g->ny, INV_MAX_PARTS);
+// Partition of lb_invariants: nb blocks of rpb rows each (nb <= LBKT_INV_MAX_PARTS).
+void lbkt_inv_partition(const lb_grid* g, int* rpb, int* nb) {
+  const int nblk = std::min(g->ny, LBKT_INV_MAX_PARTS);
   *rpb = (g->ny + nblk - 1) / nblk;
   *nb = (g->ny + *rpb - 1) / *rpb;
 }
 
+// Argument checks of lb_invariants (shared with its variant without allocation).
+lb_status lbkt_invariants_args(const lb_grid* g, lb_prec prec, const void* f, const double* out4) {
+  lb_status s;
+  if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(f, "f"))) return s;
+  if (!out4) return fail(LB_EINVAL, "out4 is NULL");
+  return LB_OK;
+}
+
 // The two kernels of lb_invariants over a partial-sum buffer of nb * 4 doubles.
-static lb_status launch_invariants(const KTConsts& K, lb_prec prec, const void* f, int rpb, int nb, double* part,
-                                   double* out4, hipStream_t st) {
+lb_status lbkt_launch_invariants(const KTConsts& K, lb_prec prec, const void* f, int rpb, int nb, double* part,
+                                 double* out4, hipStream_t st) {
   if (prec == LB_F64)
     hipLaunchKernelGGL(k_inv_partial<double>, dim3(nb), dim3(256), 0, st, K, (const double*)f, rpb, part);
   else
@@ -1829,12 +1835,11 @@ std::map<int, Workspace> g_ws;
 
 extern "C" lb_status lb_invariants(const lb_grid* g, lb_prec prec, const void* f, double* out4, void* stream) {
   lb_status s;
-  if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(f, "f"))) return s;
-  if (!out4) return fail(LB_EINVAL, "out4 is NULL");
+  if ((s = lbkt_invariants_args(g, prec, f, out4))) return s;
   KTConsts K;
   build_consts(g, &K);
   int rpb, nb;
-  inv_partition(g, &rpb, &nb);
+  lbkt_inv_partition(g, &rpb, &nb);
   const size_t bytes = (size_t)nb * 4 * sizeof(double);
   hipStream_t st = (hipStream_t)stream;
   int dev = 0;
@@ -1856,7 +1861,7 @@ extern "C" lb_status lb_invariants(const lb_grid* g, lb_prec prec, const void* f
   } else {
     HIP_CHECK(hipStreamWaitEvent(st, w.last, 0));
   }
-  if ((s = launch_invariants(K, prec, f, rpb, nb, (double*)w.ptr, out4, st))) return s;
+  if ((s = lbkt_launch_invariants(K, prec, f, rpb, nb, (double*)w.ptr, out4, st))) return s;
   HIP_CHECK(hipEventRecord(w.last, st));
   return LB_OK;
 }
