@@ -19,6 +19,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -64,9 +65,50 @@ def fields_to(dev, fields):
     return [torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev) for a in fields]
 
 
-def time_step(prec, steps, warmup, dev, per_pass=2):
+def replays(s, replay, settle_ms=250.0, reps=7):
+    """Time `reps` calls of replay() (each one graph replay, or one fixed batch of
+    launches, on stream s), each bracketed by HIP events and a device
+    synchronisation, after untimed calls that keep the GPU busy for at least
+    settle_ms (the first work after the GPU has idled runs up to 20% slower while
+    its clocks come up). Returns the per-call times in ms (in call order)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 0
+    while n < 2 or (time.perf_counter() - t0) * 1e3 < settle_ms:
+        replay()
+        torch.cuda.synchronize()
+        n += 1
+    out = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        replay()
+        e1.record(s)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return out
+
+
+def median(v):
+    w = sorted(v)
+    return w[len(w) // 2] if len(w) % 2 else 0.5 * (w[len(w) // 2 - 1] + w[len(w) // 2])
+
+
+def spread(v):
+    """min / median / max of a list of times and the relative range."""
+    m = median(v)
+    return {"min": min(v), "median": m, "max": max(v), "rel_range": (max(v) - min(v)) / m, "n": len(v)}
+
+
+def time_step(prec, steps, warmup, dev, per_pass=2, long_ms=20.0):
     """lb_run on the roofline grid with `per_pass` time steps per launch (steps a
-    multiple of 4, so that a two-step run is all two-step passes)."""
+    multiple of 4, so that a two-step run is all two-step passes): W warm-up steps,
+    the K-step graph captured, then the median of 7 replays of exactly K steps
+    (after the settle replays); as a check, the median of 5 replays of a graph of
+    K_long >= K steps lasting at least long_ms each."""
     import torch
     import paper_0706_0405_amd as lb
     from workloads import problems as P
@@ -79,25 +121,23 @@ def time_step(prec, steps, warmup, dev, per_pass=2):
         fa = lb.init(g, rho, ux, uy, p, prec=prec)
         fb = lb.empty(g, prec, dev)
         del rho, ux, uy, p
-        tile = None
         if warmup > 0:
-            lb.run(g, fa, fb, warmup, prec=prec, tile=tile, steps_per_pass=per_pass)
-        # capture the K-step graph once (untimed), then time one replay
-        lb.run(g, fa, fb, steps, prec=prec, use_graph=True, tile=tile, steps_per_pass=per_pass)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        out = lb.run(g, fa, fb, steps, prec=prec, use_graph=True, tile=tile, steps_per_pass=per_pass)
-        e1.record(s)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        _, _, _, _, flags = lb.moments(g, out, prec=prec)
+            lb.run(g, fa, fb, warmup, prec=prec, steps_per_pass=per_pass)
+        run_k = lambda: lb.run(g, fa, fb, steps, prec=prec, use_graph=True, steps_per_pass=per_pass)  # noqa: E731
+        run_k()   # capture (untimed)
+        times = replays(s, run_k)
+        ms = median(times)
+        k_long = steps * max(1, math.ceil(long_ms / ms))   # a multiple of 4: the result stays in fa
+        run_long = lambda: lb.run(g, fa, fb, k_long, prec=prec, use_graph=True, steps_per_pass=per_pass)  # noqa: E731
+        run_long()
+        long_times = replays(s, run_long, settle_ms=0.0, reps=5)
+        _, _, _, _, flags = lb.moments(g, fa, prec=prec)
         torch.cuda.synchronize()
     sites = g.nx * g.ny
     launches = steps // per_pass
     per_launch_ms = ms / launches
     mlups = sites * steps / (ms * 1e-3) / 1e6
+    long_mlups = sites * k_long / (median(long_times) * 1e-3) / 1e6
     achieved = BYTES_PER_SITE[prec] * sites / (per_launch_ms * 1e-3) / 1e9
     kname = "k_step" if per_pass == 1 else "k_step2"
     traffic = measured_traffic(kname, prec)
@@ -107,13 +147,16 @@ def time_step(prec, steps, warmup, dev, per_pass=2):
         "mlups": mlups, "ms_per_step": ms / steps, "steps_per_pass": per_pass, "grid": [g.nx, g.ny],
         "flags": [int(v) for v in flags.cpu().tolist()],
         "mlups_vs_one_step_hbm_bound": mlups / bound_mlups,
+        "replays": {"steps_each": steps, "ms": spread(times),
+                    "check_long": {"steps_each": k_long, "ms": spread(long_times), "mlups": long_mlups,
+                                   "ratio_to_value": long_mlups / mlups}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "%s<%s>" % (kname, "double" if prec == "f64" else "float"),
                      "launch_ms": per_launch_ms,
                      "algorithmic_bytes_per_launch": BYTES_PER_SITE[prec] * sites},
     }
-    del fa, fb, out
+    del fa, fb
     torch.cuda.empty_cache()
     return res
 
@@ -167,14 +210,18 @@ def bench_batched(dev, steps=2000, nprob=256):
         block_x = tuning.batch_block_for(B, fa, fb)   # block width chosen by timing (cached per device)
         init_all()
         B.step(fa, fb, steps)           # capture + first replay (untimed)
-        init_all()
-        torch.cuda.synchronize()
+        B.step(fa, fb, steps)           # settle (untimed)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        out = B.step(fa, fb, steps)
-        e1.record(s)
-        torch.cuda.synchronize()
-        t_batch = e0.elapsed_time(e1)
+        times = []
+        for _ in range(5):              # five timed replays, each from the initial fields
+            init_all()
+            torch.cuda.synchronize()
+            e0.record(s)
+            out = B.step(fa, fb, steps)
+            e1.record(s)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        t_batch = median(times)
         nonfinite = 0
         for k, g in enumerate(grids):
             _, _, _, _, fl = lb.moments(g, B.view(out, k), prec="f32")
@@ -200,7 +247,8 @@ def bench_batched(dev, steps=2000, nprob=256):
     sites = sum(g.nx * g.ny for g in grids)
     mlups = sites * steps / (t_batch * 1e-3) / 1e6
     return {"problems": nprob, "steps": steps, "sites": sites, "draws": info, "block_x": block_x,
-            "batched_ms": t_batch, "single_sum_ms": t_single, "speedup": t_single / t_batch,
+            "batched_ms": t_batch, "batched_ms_replays": spread(times),
+            "single_sum_ms": t_single, "speedup": t_single / t_batch,
             "batched_mlups": mlups, "steps_per_pass": 2,
             "mlups_vs_one_step_hbm_bound": mlups * 1e6 * BYTES_PER_SITE["f32"] / (HBM_PEAK_GBS * 1e9),
             "nonfinite_problems": nonfinite}
@@ -224,22 +272,19 @@ def bench_adjoint_step(dev, fwd_ms, nsteps=20):
         ga = lb.empty(g, "f64", dev)
         ga.normal_()
         gb = lb.empty(g, "f64", dev)
-        states = [f] * nsteps
-        api.adjoint_run(g, states, ga, gb, prec="f32")   # warm
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        out = api.adjoint_run(g, states, ga, gb, prec="f32")
-        e1.record(s)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / nsteps
+        states = [f] * nsteps   # nsteps adjoint steps, direct launches (no graph)
+        times = replays(s, lambda: api.adjoint_run(g, states, ga, gb, prec="f32"))
+        out = ga if nsteps % 2 == 0 else gb
+        ms = median(times) / nsteps
         finite = bool(torch.isfinite(out[:, :, :g.nx]).all())
         del f, ga, gb, out, states
     torch.cuda.empty_cache()
     sites = g.nx * g.ny
     achieved = 180 * sites / (ms * 1e-3) / 1e9
     return {"grid": [g.nx, g.ny], "kernel": "k_adjoint<float>", "ms_per_step": ms,
-            "mlups": sites / (ms * 1e-3) / 1e6, "forward_ms_per_step": fwd_ms, "ratio": ms / fwd_ms,
+            "replays_ms": spread([t / nsteps for t in times]),
+            "mlups": sites / (ms * 1e-3) / 1e6, "forward_ms_per_step": fwd_ms,
+            "ratio": ms / fwd_ms if fwd_ms else None,
             "ratio_by_bytes": 180 / 72, "achieved_gbs": achieved, "roofline_frac": achieved / HBM_PEAK_GBS,
             "finite": finite}
 
@@ -330,16 +375,11 @@ def bench_configs(dev, max_steps=4000):
             fa = lb.init(g, rho, ux, uy, p, prec=prec)
             fb = lb.empty(g, prec, dev)
             lb.run(g, fa, fb, steps, prec=prec, use_graph=True)   # capture + first replay
-            lb.init(g, rho, ux, uy, p, prec=prec, out=fa)          # same buffers: the graph is reused
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(s)
-            lb.run(g, fa, fb, steps, prec=prec, use_graph=True)
-            e1.record(s)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
+            times = replays(s, lambda: lb.run(g, fa, fb, steps, prec=prec, use_graph=True), settle_ms=50.0, reps=5)
+            ms = median(times)
         out.append({"case": name, "grid": [g.nx, g.ny], "storage": prec, "steps": steps,
-                    "ms_per_step": ms / steps, "mlups": g.nx * g.ny * steps / (ms * 1e-3) / 1e6})
+                    "ms_per_step": ms / steps, "mlups": g.nx * g.ny * steps / (ms * 1e-3) / 1e6,
+                    "replays_rel_range": spread(times)["rel_range"]})
     return out
 
 
@@ -360,29 +400,41 @@ def bench_adjoint(dev, steps=2000):
         target = R.forward_density(rho * 1.001).detach()
         fa = lb.init(g, rho, ux, uy, p, prec="f32")
         fb = lb.empty(g, "f32", dev)
-        lb.run(g, fa, fb, steps, prec="f32")   # warm
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fa = lb.init(g, rho, ux, uy, p, prec="f32")
-        lb.run(g, fa, fb, steps, prec="f32")
-        torch.cuda.synchronize()
-        t_fwd = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        fa = lb.init(g, rho, ux, uy, p, prec="f32")
-        lb.run(g, fa, fb, steps, prec="f32", steps_per_pass=1)
-        torch.cuda.synchronize()
-        t_fwd1 = time.perf_counter() - t0
+
+        def wall(fn, reps=5):
+            """Median host wall time of fn() (ended by a device synchronisation)
+            over `reps` calls after one untimed call."""
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            return median(ts), ts
+
+        def fwd(spp):
+            lb.init(g, rho, ux, uy, p, prec="f32", out=fa)
+            lb.run(g, fa, fb, steps, prec="f32", steps_per_pass=spp)
+
+        t_fwd, ts_fwd = wall(lambda: fwd(0))
+        t_fwd1, _ = wall(lambda: fwd(1))
         r0 = rho.clone().requires_grad_(True)
-        R.loss_and_grad(r0, target)            # warm
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        loss, grad = R.loss_and_grad(r0, target)
-        torch.cuda.synchronize()
-        t_grad = time.perf_counter() - t0
+        res = {}
+
+        def grad_once():
+            res["loss"], res["grad"] = R.loss_and_grad(r0, target)
+
+        t_grad, ts_grad = wall(grad_once)
+        grad = res["grad"]
     return {"grid": [g.nx, g.ny], "steps": steps, "checkpoint_every": R.seg, "forward_ms": t_fwd * 1e3,
             "gradient_ms": t_grad * 1e3, "ratio": t_grad / t_fwd,
             "forward_one_step_per_launch_ms": t_fwd1 * 1e3, "ratio_vs_one_step_forward": t_grad / t_fwd1,
-            "grad_finite": bool(torch.isfinite(grad).all())}
+            "grad_finite": bool(torch.isfinite(grad).all()),
+            "timing": "median host wall time of 5 calls after one untimed call",
+            "forward_ms_range": [min(ts_fwd) * 1e3, max(ts_fwd) * 1e3],
+            "gradient_ms_range": [min(ts_grad) * 1e3, max(ts_grad) * 1e3]}
 
 
 def cpu_baseline(target_s=15.0):
@@ -467,7 +519,12 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--prec", choices=["f64", "f32", "both"], default="both")
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated subset of step,batched,adjoint,adjoint_step,vn,configs (for profiling "
+                         "one leg; without 'step' the line carries no headline value)")
     args = ap.parse_args()
+    legs = {"step", "batched", "adjoint", "adjoint_step", "vn", "configs"} if args.legs == "all" \
+        else set(args.legs.split(","))
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -483,7 +540,7 @@ def main():
     dev = torch.device("cuda", 0)
 
     res, one = {}, {}
-    for prec in (("f64", "f32") if args.prec == "both" else (args.prec,)):
+    for prec in (("f64", "f32") if args.prec == "both" else (args.prec,)) if "step" in legs else ():
         log("timing", prec, "lb_run on the roofline grid, two steps per pass")
         res[prec] = time_step(prec, args.steps, args.warmup, dev, per_pass=2)
         log(prec, json.dumps(res[prec]))
@@ -491,35 +548,42 @@ def main():
         one[prec] = time_step(prec, args.steps, args.warmup, dev, per_pass=1)
         log(prec, json.dumps(one[prec]))
     head = "f64" if "f64" in res else "f32"
-    log("timing a device copy of the same size")
-    copy = copy_bandwidth(dev)
-    for r_ in list(res.values()) + list(one.values()):
-        r_["roofline"]["frac_of_device_copy"] = r_["roofline"]["achieved"] / copy["gbs"]
+    copy = None
+    if res:
+        log("timing a device copy of the same size")
+        copy = copy_bandwidth(dev)
+        for r_ in list(res.values()) + list(one.values()):
+            r_["roofline"]["frac_of_device_copy"] = r_["roofline"]["achieved"] / copy["gbs"]
     extras = {}
     if not args.no_extras:
-        log("timing batched problems")
-        extras["batched"] = bench_batched(dev)
-        log(json.dumps(extras["batched"]))
-        try:
+        if "batched" in legs:
+            log("timing batched problems")
+            extras["batched"] = bench_batched(dev)
+            log(json.dumps(extras["batched"]))
+        if "adjoint" in legs:
             log("timing adjoint")
             extras["adjoint"] = bench_adjoint(dev)
             log(json.dumps(extras["adjoint"]))
-        except ImportError as e:
-            extras["adjoint"] = {"error": str(e)}
-        if "f32" in one:
+        if "adjoint_step" in legs:
             log("timing one adjoint step on the roofline grid")
-            extras["adjoint_step"] = bench_adjoint_step(dev, one["f32"]["ms_per_step"])
+            fwd = one["f32"]["ms_per_step"] if "f32" in one else None
+            extras["adjoint_step"] = bench_adjoint_step(dev, fwd)
             log(json.dumps(extras["adjoint_step"]))
-        log("timing the von Neumann chooser")
-        extras["vn_scan"] = bench_vn(dev)
-        log(json.dumps(extras["vn_scan"]))
-        log("timing the small configurations at their own sizes")
-        extras["configs"] = bench_configs(dev)
-        log(json.dumps(extras["configs"]))
+        if "vn" in legs:
+            log("timing the von Neumann chooser")
+            extras["vn_scan"] = bench_vn(dev)
+            log(json.dumps(extras["vn_scan"]))
+        if "configs" in legs:
+            log("timing the small configurations at their own sizes")
+            extras["configs"] = bench_configs(dev)
+            log(json.dumps(extras["configs"]))
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and res:
         log("timing CPU oracle sample")
         cpu = cpu_baseline()
+    if not res:   # a partial run (profiling one leg): no headline
+        print(json.dumps({"partial_run": sorted(legs), **extras}), flush=True)
+        return
     r = res[head]
     line = {
         "metric": "MLUPS vs HBM roofline (fp64/fp32); batched speedup; adjoint/forward ratio",
@@ -529,6 +593,7 @@ def main():
         "config": {"workload": "double-Mach-reflection field, %dx%d grid, FP64 storage, FDLB steps through lb_run "
                                "(two time steps per pass)" % tuple(r["grid"]), "storage": head, "steps_per_pass": 2},
         "roofline": r["roofline"],
+        "replays": r["replays"],
         "mlups_vs_one_step_hbm_bound": r["mlups_vs_one_step_hbm_bound"],
         "one_step_per_launch": {p: {"value": one[p]["mlups"], "unit": "MLUPS", "ms_per_step": one[p]["ms_per_step"],
                                     "roofline": one[p]["roofline"]} for p in one},
@@ -539,6 +604,7 @@ def main():
         line["fp32_storage"] = {"value": res["f32"]["mlups"], "unit": "MLUPS", "ms_per_step": res["f32"]["ms_per_step"],
                                 "dtype": "f64 arithmetic, f32 storage", "steps_per_pass": 2,
                                 "mlups_vs_one_step_hbm_bound": res["f32"]["mlups_vs_one_step_hbm_bound"],
+                                "replays": res["f32"]["replays"],
                                 "roofline": res["f32"]["roofline"]}
     line.update(extras)
     print(json.dumps(line), flush=True)

@@ -76,6 +76,9 @@ typedef enum {
   LB_EUNSUPPORTED = -7 /* valid request the library does not implement */
 } lb_status;
 
+/* Storage precision. Entry points take it as an int32_t `prec` holding one of
+ * these codes (as lb_edge.kind holds an lb_bc_kind): any other value returns
+ * LB_EINVAL. */
 typedef enum { LB_F64 = 0, LB_F32 = 1 } lb_prec;
 
 typedef enum {
@@ -141,17 +144,17 @@ int64_t lb_array_elems(const lb_grid* grid);
 
 /* Initialisation (Sec. 4.2: the field starts at equilibrium): f := f^eq(rho, u, p/rho)
  * from dense float64 device fields. f has the storage type of `prec`. */
-lb_status lb_init(const lb_grid* grid, lb_prec prec, const double* rho, const double* ux,
+lb_status lb_init(const lb_grid* grid, int32_t prec, const double* rho, const double* ux,
                   const double* uy, const double* p, void* f, void* stream);
 
 /* One time step f_out = S(f_in) at time index `step` (t = step*dt, used by SHOCK
  * edges). f_in and f_out must not overlap. */
-lb_status lb_step(const lb_grid* grid, lb_prec prec, const void* f_in, void* f_out, int64_t step,
+lb_status lb_step(const lb_grid* grid, int32_t prec, const void* f_in, void* f_out, int64_t step,
                   void* stream);
 
 /* lb_step with an explicit launch shape (tile NULL = default). Every tile gives
  * bitwise the same result. */
-lb_status lb_step_tiled(const lb_grid* grid, lb_prec prec, const void* f_in, void* f_out,
+lb_status lb_step_tiled(const lb_grid* grid, int32_t prec, const void* f_in, void* f_out,
                         int64_t step, const lb_tile* tile, void* stream);
 
 /* nsteps ping-pong steps from f_a at time index step0. The result is in f_a when
@@ -160,14 +163,14 @@ lb_status lb_step_tiled(const lb_grid* grid, lb_prec prec, const void* f_in, voi
  * use_graph != 0 captures the launches in a HIP graph (cached: a repeated call with
  * the same arguments replays it). Every launch shape and steps setting gives
  * bitwise the same result. */
-lb_status lb_run(const lb_grid* grid, lb_prec prec, void* f_a, void* f_b, int64_t step0,
+lb_status lb_run(const lb_grid* grid, int32_t prec, void* f_a, void* f_b, int64_t step0,
                  int32_t nsteps, int32_t use_graph, const lb_tile* tile, void* stream);
 
 /* Moments of f (Eqs. (e4), (e5), (e7)) into dense float64 device fields (any of
  * rho/ux/uy/T may be NULL), and, if flags != NULL, a device uint32[4]:
  * flags[0] = OR of LB_FLAG_* over all sites, flags[1..3] = number of sites that are
  * non-finite, have rho <= 0, have T <= 0. The flags array is cleared by the call. */
-lb_status lb_moments(const lb_grid* grid, lb_prec prec, const void* f, double* rho, double* ux,
+lb_status lb_moments(const lb_grid* grid, int32_t prec, const void* f, double* rho, double* ux,
                      double* uy, double* T, uint32_t* flags, void* stream);
 
 /* Blow-up as a status (Sec. 3: outside its linear-stability range the scheme
@@ -187,7 +190,7 @@ lb_status lb_check_flags(const uint32_t* flags, uint32_t* host_flags, void* stre
  * on first use (and grown when a larger grid needs more partial sums); calls on
  * different streams are ordered on it (each waits for the previous call's
  * kernels before writing it). */
-lb_status lb_invariants(const lb_grid* grid, lb_prec prec, const void* f, double* out4,
+lb_status lb_invariants(const lb_grid* grid, int32_t prec, const void* f, double* out4,
                         void* stream);
 
 /* lb_invariants for callers that cannot allocate device memory (code under HIP
@@ -202,7 +205,7 @@ lb_status lb_invariants(const lb_grid* grid, lb_prec prec, const void* f, double
  * threads) race on it. LB_EINVAL if the grid needs more than 4096 partial
  * records (the partition never does: it caps the number of row blocks at 4096),
  * and the argument errors of lb_invariants. */
-lb_status lb_invariants_noalloc(const lb_grid* grid, lb_prec prec, const void* f, double* out4,
+lb_status lb_invariants_noalloc(const lb_grid* grid, int32_t prec, const void* f, double* out4,
                                 void* stream);
 
 /* Adjoint (vector-Jacobian product) of lb_step at f_n: g_n = (dS/df)^T g_np1.
@@ -211,7 +214,7 @@ lb_status lb_invariants_noalloc(const lb_grid* grid, lb_prec prec, const void* f
  * identity). g_np1 and g_n must not overlap. The paper has no adjoint: this is
  * the exact transpose of the step's linearisation (upwinding by the fixed sign
  * of v, no limiter, so the step is smooth in f where rho != 0). */
-lb_status lb_step_adjoint(const lb_grid* grid, lb_prec prec, const void* f_n, const double* g_np1,
+lb_status lb_step_adjoint(const lb_grid* grid, int32_t prec, const void* f_n, const double* g_np1,
                           double* g_n, int64_t step, void* stream);
 
 /* nsteps steps from f0, keeping every state: out[j] (a host array of nsteps
@@ -222,7 +225,7 @@ lb_status lb_step_adjoint(const lb_grid* grid, lb_prec prec, const void* f_n, co
  * (bitwise the state of a single step), wherever the pass's input and both of
  * its outputs are distinct arrays below 4 GiB and ny >= 2; elsewhere one step
  * per launch. */
-lb_status lb_run_record(const lb_grid* grid, lb_prec prec, const void* f0, void* const* out, int64_t step0,
+lb_status lb_run_record(const lb_grid* grid, int32_t prec, const void* f0, void* const* out, int64_t step0,
                         int32_t nsteps, void* stream);
 
 /* Reverse sweep over nsteps steps: f[j] (host array of nsteps device pointers) is
@@ -230,7 +233,7 @@ lb_status lb_run_record(const lb_grid* grid, lb_prec prec, const void* f0, void*
  * lb_step_adjoint for j = nsteps-1 .. 0, alternating between g and work (both
  * float64 distribution arrays, not overlapping); g^{step0} ends in g when nsteps
  * is even, else in work. */
-lb_status lb_adjoint_run(const lb_grid* grid, lb_prec prec, const void* const* f, double* g, double* work,
+lb_status lb_adjoint_run(const lb_grid* grid, int32_t prec, const void* const* f, double* g, double* work,
                          int64_t step0, int32_t nsteps, void* stream);
 
 /* Adjoint of lb_init with respect to rho at fixed u and p:
@@ -247,7 +250,7 @@ typedef struct lb_batch lb_batch;
  * recomputed). Uploads per-problem constants and a work list. Errors as
  * lb_validate, LB_EUNSUPPORTED for a SHOCK edge or a problem whose array
  * reaches 4 GiB. */
-lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, lb_prec prec, lb_batch** out);
+lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, int32_t prec, lb_batch** out);
 
 /* Element offset of each problem's array inside the packed array (host int64[nprob])
  * and the total element count; each problem p is a normal distribution array with
@@ -275,7 +278,7 @@ void lb_batch_destroy(lb_batch* b);
  * and for two steps per pass, and return the fastest per time step in *best
  * (best->steps tells which; pass it to lb_run as is) and its time per step in
  * *best_ms; f_a/f_b are scratch state. Synchronises `stream`. */
-lb_status lb_autotune(const lb_grid* grid, lb_prec prec, void* f_a, void* f_b, int32_t reps,
+lb_status lb_autotune(const lb_grid* grid, int32_t prec, void* f_a, void* f_b, int32_t reps,
                       lb_tile* best, float* best_ms, void* stream);
 
 /* ------------------------------------------------------------ von Neumann scan
@@ -332,7 +335,7 @@ lb_status lb_vn_max_stable_dt(const lb_vn_case* cases, int32_t ncases, const dou
  * other values. */
 int64_t lb_struct_size(int32_t which);
 
-const char* lb_status_str(lb_status s);
+const char* lb_status_str(int32_t status);
 const char* lb_last_error(void);
 
 #ifdef __cplusplus

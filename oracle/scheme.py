@@ -179,9 +179,20 @@ def step_rows(pb: Problem, f, n: int, rows):
     return torch.stack(out)
 
 
-def run(pb: Problem, f, nsteps: int, n0: int = 0):
+def store(f, storage=None):
+    """f as held in memory between steps: unchanged for float64 storage; for float32
+    storage each value rounded to the nearest float32 (and read back exactly), the
+    arithmetic of every step staying in float64."""
+    if storage is None or storage == torch.float64:
+        return f
+    return f.to(storage).to(F64)
+
+
+def run(pb: Problem, f, nsteps: int, n0: int = 0, storage=None):
+    """nsteps steps from f at time index n0; `storage` (None or torch.float32) rounds
+    every stored state as in `store` (pass f already stored)."""
     for n in range(n0, n0 + nsteps):
-        f = step(pb, f, n)
+        f = store(step(pb, f, n), storage)
     return f
 
 

@@ -71,6 +71,41 @@ def max_modulus(state, params, kdx, kdy, J=None) -> float:
     return float(torch.linalg.eigvals(G).abs().max())
 
 
+def amplification_many(state, params, kdx, kdy, J=None):
+    """G(k) of `amplification` for a list of wave vectors at once: (n, 9, 9) complex128.
+
+    The same formula with the Eq. (SEC-VON-9) factors and the dissipation term
+    evaluated per wave vector as tensors (kdx, kdy: sequences of k dx, k dy)."""
+    c1, c2, eta0, gamma = params["c1"], params["c2"], params["eta0"], params["gamma"]
+    tau, beta, dt, dx, lam = params["tau"], params["beta"], params["dt"], params["dx"], params["lam"]
+    if J is None:
+        J = collision_jacobian(*state, c1, c2, eta0, gamma)
+    kx = torch.as_tensor(kdx, dtype=F64)
+    ky = torch.as_tensor(kdy, dtype=F64)
+    n = kx.numel()
+    v = kt.velocities(c1, c2)
+
+    def phis(vc, k):
+        ep, em = torch.exp(1j * k), torch.exp(-1j * k)
+        if vc >= 0:
+            return beta * ep + (1.0 - 2.0 * beta) - (1.0 - beta) * em
+        return (1.0 - beta) * ep - (1.0 - 2.0 * beta) - beta * em
+
+    G = (J / tau).to(torch.complex128).expand(n, 9, 9).clone()
+    for i in range(9):
+        vx, vy = float(v[i, 0]), float(v[i, 1])
+        conv = vx * dt / dx * phis(vx, kx) + vy * dt / dx * phis(vy, ky)
+        diss = lam[i] * ((2 - 2 * torch.cos(kx)) + (2 - 2 * torch.cos(ky))) * dt / dx ** 2
+        G[:, i, i] += 1.0 - 1.0 / tau - conv - diss
+    return G
+
+
+def max_modulus_many(state, params, kdx, kdy, J=None) -> float:
+    """max over the wave vectors of the spectral radius of G(k)."""
+    G = amplification_many(state, params, kdx, kdy, J)
+    return float(torch.linalg.eigvals(G).abs().max())
+
+
 def scan_diagonal(state, params, npts: int = 31):
     """max|omega| over k = (k, k), k dx in {0, pi/30, ..., pi} (the k grid of Sec. 3)."""
     J = collision_jacobian(*state, params["c1"], params["c2"], params["eta0"], params["gamma"])

@@ -211,12 +211,15 @@ static int shock_cells(const lb_grid* g, int e, int64_t step) {
   const double t = (double)step * g->dt;
   const double xs = E.x0 + yg / std::tan(ang) + E.speed * t / std::sin(ang);
   const double q = xs / g->dx - 0.5;
-  int n = (q <= 0.0) ? 0 : (q >= (double)g->nx ? g->nx : (int)std::ceil(q));
+  // !(q > 0) also catches a NaN position (an infinite shock geometry): no cell behind
+  int n = !(q > 0.0) ? 0 : (q >= (double)g->nx ? g->nx : (int)std::ceil(q));
   // settle the boundary cell with the exact predicate
   while (n > 0 && !(((double)(n - 1) + 0.5) * g->dx < xs)) --n;
   while (n < g->nx && ((double)n + 0.5) * g->dx < xs) ++n;
   return n;
 }
+
+int lbkt_shock_cells(const lb_grid* g, int edge, int64_t step) { return shock_cells(g, edge, step); }
 
 // ------------------------------------------------------------------ device: loads
 
@@ -1346,10 +1349,7 @@ __global__ __launch_bounds__(256) void k_init_adjoint(KTConsts K, const double* 
 
 // ------------------------------------------------------------------ batched
 
-struct WorkItem {
-  int32_t prob;
-  int32_t strip;
-};
+using WorkItem = LbktWorkItem;
 
 struct ProbInfo {
   int64_t offset;   // element offset of the problem's array in the packed buffer
@@ -1477,6 +1477,9 @@ static lb_status check_ptr(const void* p, const char* what) {
   return LB_OK;
 }
 
+// ceil(a / b) for a >= 0, b > 0 without int overflow (ny may be up to 2^31 - 1).
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = (const char*)a;
   const char* pb = (const char*)b;
@@ -1493,7 +1496,7 @@ struct Tile {
 // tile shrinks (rows first, down to 2, then columns) until there are at least
 // 1024 tiles, four per compute unit.
 static void default_tile(int nx, int ny, int* bx, int* rows, int min_tiles = 1024) {
-  auto ntiles = [&](int b, int r) { return (int64_t)((nx + b - 1) / b) * ((ny + r - 1) / r); };
+  auto ntiles = [&](int b, int r) { return cdiv(nx, b) * cdiv(ny, r); };
   int b = 256, r = 32;
   while (ntiles(b, r) < min_tiles && r > 2) r /= 2;
   while (ntiles(b, r) < min_tiles && b > 64) b /= 2;
@@ -1509,7 +1512,7 @@ static void default_tile(int nx, int ny, int* bx, int* rows, int min_tiles = 102
 // the paper's 200x4 .. 960x240 configurations against the autotuner).
 static void default_tile2(int nx, int ny, lb_prec prec, int* bx, int* rows) {
   auto ntiles = [&](int b, int r) {
-    return (int64_t)(((nx + 59) / 60 + b / 64 - 1) / (b / 64)) * ((ny + r - 1) / r);
+    return cdiv(cdiv(nx, 60), b / 64) * cdiv(ny, r);
   };
   int b = 256, r = prec == LB_F64 ? 11 : 24;
   while (ntiles(b, r) < 1024 && r > 2) r = std::max(2, r / 2);
@@ -1518,6 +1521,8 @@ static void default_tile2(int nx, int ny, lb_prec prec, int* bx, int* rows) {
   *bx = b;
   *rows = std::min(r, ny);
 }
+
+void lbkt_default_tile2(int nx, int ny, lb_prec prec, int* bx, int* rows) { default_tile2(nx, ny, prec, bx, rows); }
 
 static lb_status resolve_tile(const lb_tile* tile, int nx, int ny, Tile* t) {
   int b, r, nb = 0;
@@ -1546,10 +1551,9 @@ static lb_status launch_step(const lb_grid* g, const KTConsts& K, lb_prec prec, 
                              int64_t step, const Tile& t, hipStream_t st) {
   const bool w = wide(g, elem_size(prec));
   const int bx = t.bx, rows = w ? std::min(t.rows, wide_max_rows(g, elem_size(prec))) : t.rows;
-  const int nstrips = (g->nx + bx - 1) / bx;
-  const int nchunks = (g->ny + rows - 1) / rows;
-  const int64_t ntiles64 = (int64_t)nstrips * nchunks;
+  const int64_t ntiles64 = cdiv(g->nx, bx) * cdiv(g->ny, rows);
   if (ntiles64 > 0x7fffffff) return fail(LB_EINVAL, "grid too large for one launch");
+  const int nstrips = (int)cdiv(g->nx, bx);
   const int ntiles = (int)ntiles64;
   // tile order: double storage runs fastest in plain raster order (the whole
   // chip on a narrow band of rows: the rows shared by vertically adjacent tiles
@@ -1582,10 +1586,8 @@ static lb_status launch_step2(const lb_grid* g, const KTConsts& K, lb_prec prec,
   if (!t.user) default_tile2(g->nx, g->ny, prec, &bx, &rows);
   if (w) rows = std::min(rows, wide_max_rows(g, elem_size(prec)) - 2);   // >= 1 (launch_steps)
   const int wpb = bx / 64;
-  const int nwaves = (g->nx + 59) / 60;   // 60 output columns per wavefront
-  const int nstrips = (nwaves + wpb - 1) / wpb;
-  const int nchunks = (g->ny + rows - 1) / rows;
-  const int64_t ntiles64 = (int64_t)nstrips * nchunks;
+  const int nstrips = (int)cdiv(cdiv(g->nx, 60), wpb);   // 60 output columns per wavefront
+  const int64_t ntiles64 = (int64_t)nstrips * cdiv(g->ny, rows);
   if (ntiles64 > 0x7fffffff) return fail(LB_EINVAL, "grid too large for one launch");
   const int ntiles = (int)ntiles64;
   const int xcd_map = 0;   // raster order (the XCD bands measured 5-10% slower here)
@@ -1627,15 +1629,19 @@ static lb_status launch_steps(const lb_grid* g, const KTConsts& K, lb_prec prec,
   return LB_OK;
 }
 
-static lb_status check_prec(lb_prec p) {
+// The C ABI passes precisions as int32_t codes (any value a C caller may pass is
+// then defined); a code becomes an lb_prec only after this check.
+static lb_status check_prec(int32_t p) {
   if (p != LB_F64 && p != LB_F32) return fail(LB_EINVAL, "unknown precision");
   return LB_OK;
 }
 
 // ------------------------------------------------------------------ C ABI
 
-extern "C" lb_status lb_init(const lb_grid* g, lb_prec prec, const double* rho, const double* ux,
+extern "C" lb_status lb_init(const lb_grid* g, int32_t prec_code, const double* rho, const double* ux,
                              const double* uy, const double* p, void* f, void* stream) {
+  if (check_prec(prec_code)) return LB_EINVAL;
+  const lb_prec prec = (lb_prec)prec_code;
   lb_status s;
   if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(f, "f"))) return s;
   if (!rho || !ux || !uy || !p) return fail(LB_EINVAL, "field pointer is NULL");
@@ -1651,8 +1657,10 @@ extern "C" lb_status lb_init(const lb_grid* g, lb_prec prec, const double* rho, 
   return LB_OK;
 }
 
-extern "C" lb_status lb_step_tiled(const lb_grid* g, lb_prec prec, const void* fin, void* fout, int64_t step,
+extern "C" lb_status lb_step_tiled(const lb_grid* g, int32_t prec_code, const void* fin, void* fout, int64_t step,
                                    const lb_tile* tile, void* stream) {
+  if (check_prec(prec_code)) return LB_EINVAL;
+  const lb_prec prec = (lb_prec)prec_code;
   lb_status s;
   if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(fin, "f_in")) ||
       (s = check_ptr(fout, "f_out")))
@@ -1666,9 +1674,9 @@ extern "C" lb_status lb_step_tiled(const lb_grid* g, lb_prec prec, const void* f
   return launch_step(g, K, prec, fin, fout, step, t, (hipStream_t)stream);
 }
 
-extern "C" lb_status lb_step(const lb_grid* g, lb_prec prec, const void* fin, void* fout, int64_t step,
+extern "C" lb_status lb_step(const lb_grid* g, int32_t prec_code, const void* fin, void* fout, int64_t step,
                              void* stream) {
-  return lb_step_tiled(g, prec, fin, fout, step, nullptr, stream);
+  return lb_step_tiled(g, prec_code, fin, fout, step, nullptr, stream);
 }
 
 namespace {
@@ -1710,8 +1718,10 @@ static std::string run_key(const lb_grid* g, lb_prec prec, const void* fa, const
   return k + buf + std::to_string(dev);
 }
 
-extern "C" lb_status lb_run(const lb_grid* g, lb_prec prec, void* fa, void* fb, int64_t step0, int32_t nsteps,
+extern "C" lb_status lb_run(const lb_grid* g, int32_t prec_code, void* fa, void* fb, int64_t step0, int32_t nsteps,
                             int32_t use_graph, const lb_tile* tile, void* stream) {
+  if (check_prec(prec_code)) return LB_EINVAL;
+  const lb_prec prec = (lb_prec)prec_code;
   lb_status s;
   if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(fa, "f_a")) || (s = check_ptr(fb, "f_b")))
     return s;
@@ -1756,8 +1766,10 @@ extern "C" lb_status lb_run(const lb_grid* g, lb_prec prec, void* fa, void* fb, 
   return launch_exec(exec, done, st);
 }
 
-extern "C" lb_status lb_moments(const lb_grid* g, lb_prec prec, const void* f, double* rho, double* ux,
+extern "C" lb_status lb_moments(const lb_grid* g, int32_t prec_code, const void* f, double* rho, double* ux,
                                 double* uy, double* T, uint32_t* flags, void* stream) {
+  if (check_prec(prec_code)) return LB_EINVAL;
+  const lb_prec prec = (lb_prec)prec_code;
   lb_status s;
   if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(f, "f"))) return s;
   KTConsts K;
@@ -1795,12 +1807,12 @@ extern "C" lb_status lb_check_flags(const uint32_t* flags, uint32_t* host_flags,
 // Partition of lb_invariants: nb blocks of rpb rows each (nb <= LBKT_INV_MAX_PARTS).
 void lbkt_inv_partition(const lb_grid* g, int* rpb, int* nb) {
   const int nblk = std::min(g->ny, LBKT_INV_MAX_PARTS);
-  *rpb = (g->ny + nblk - 1) / nblk;
-  *nb = (g->ny + *rpb - 1) / *rpb;
+  *rpb = (int)cdiv(g->ny, nblk);
+  *nb = (int)cdiv(g->ny, *rpb);
 }
 
 // Argument checks of lb_invariants (shared with its variant without allocation).
-lb_status lbkt_invariants_args(const lb_grid* g, lb_prec prec, const void* f, const double* out4) {
+lb_status lbkt_invariants_args(const lb_grid* g, int32_t prec, const void* f, const double* out4) {
   lb_status s;
   if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(f, "f"))) return s;
   if (!out4) return fail(LB_EINVAL, "out4 is NULL");
@@ -1833,7 +1845,9 @@ std::mutex g_ws_mu;
 std::map<int, Workspace> g_ws;
 }  // namespace
 
-extern "C" lb_status lb_invariants(const lb_grid* g, lb_prec prec, const void* f, double* out4, void* stream) {
+extern "C" lb_status lb_invariants(const lb_grid* g, int32_t prec_code, const void* f, double* out4, void* stream) {
+  if (check_prec(prec_code)) return LB_EINVAL;
+  const lb_prec prec = (lb_prec)prec_code;
   lb_status s;
   if ((s = lbkt_invariants_args(g, prec, f, out4))) return s;
   KTConsts K;
@@ -1876,9 +1890,8 @@ static lb_status launch_adjoint(const lb_grid* g, const KTConsts& K, lb_prec pre
   const bool w = wide(g, sizeof(double));   // the adjoint arrays are double
   rows = std::min(rows, g->ny);
   if (w) rows = std::min(rows, wide_max_rows(g, sizeof(double)));
-  const int nstrips = (g->nx + bx - 1) / bx;
-  const int nchunks = (g->ny + rows - 1) / rows;
-  const int64_t nblocks64 = (int64_t)nstrips * nchunks;
+  const int nstrips = (int)cdiv(g->nx, bx);
+  const int64_t nblocks64 = (int64_t)nstrips * cdiv(g->ny, rows);
   if (nblocks64 > 0x7fffffff) return fail(LB_EINVAL, "grid too large for one launch");
   const int nblocks = (int)nblocks64;
   const int xcd_map = 0;   // raster order: 2-3% faster than the XCD bands on the 8192 x 2048 grid
@@ -1895,8 +1908,10 @@ static lb_status launch_adjoint(const lb_grid* g, const KTConsts& K, lb_prec pre
   return LB_OK;
 }
 
-extern "C" lb_status lb_step_adjoint(const lb_grid* g, lb_prec prec, const void* fn, const double* g1, double* g0,
+extern "C" lb_status lb_step_adjoint(const lb_grid* g, int32_t prec_code, const void* fn, const double* g1, double* g0,
                                      int64_t step, void* stream) {
+  if (check_prec(prec_code)) return LB_EINVAL;
+  const lb_prec prec = (lb_prec)prec_code;
   (void)step;  // the step's dependence on t (SHOCK ghosts) does not involve f
   lb_status s;
   if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(fn, "f_n")) ||
@@ -1909,8 +1924,10 @@ extern "C" lb_status lb_step_adjoint(const lb_grid* g, lb_prec prec, const void*
   return launch_adjoint(g, K, prec, fn, g1, g0, (hipStream_t)stream);
 }
 
-extern "C" lb_status lb_adjoint_run(const lb_grid* g, lb_prec prec, const void* const* f, double* gbuf,
+extern "C" lb_status lb_adjoint_run(const lb_grid* g, int32_t prec_code, const void* const* f, double* gbuf,
                                     double* work, int64_t step0, int32_t nsteps, void* stream) {
+  if (check_prec(prec_code)) return LB_EINVAL;
+  const lb_prec prec = (lb_prec)prec_code;
   (void)step0;
   lb_status s;
   if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(gbuf, "g")) || (s = check_ptr(work, "work")))
@@ -1932,8 +1949,10 @@ extern "C" lb_status lb_adjoint_run(const lb_grid* g, lb_prec prec, const void* 
   return LB_OK;
 }
 
-extern "C" lb_status lb_run_record(const lb_grid* g, lb_prec prec, const void* f0, void* const* out, int64_t step0,
+extern "C" lb_status lb_run_record(const lb_grid* g, int32_t prec_code, const void* f0, void* const* out, int64_t step0,
                                    int32_t nsteps, void* stream) {
+  if (check_prec(prec_code)) return LB_EINVAL;
+  const lb_prec prec = (lb_prec)prec_code;
   lb_status s;
   if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(f0, "f0"))) return s;
   if (nsteps < 0 || (nsteps > 0 && !out)) return fail(LB_EINVAL, "need nsteps >= 0 outputs");
@@ -2007,19 +2026,21 @@ struct lb_batch {
   hipEvent_t done = nullptr;   // recorded after each replay (the exec is destroyed after it)
 };
 
-static lb_status batch_items(lb_batch* b) {
+void lbkt_plan_batch(const lb_grid* grids, int nprob, int block_x, std::vector<LbktWorkItem>* items_out,
+                     std::vector<LbktWorkItem>* items2_out) {
   std::vector<WorkItem> items;
   // longest problems first so the tail of a launch is made of short items
-  std::vector<int> order(b->nprob);
-  for (int p = 0; p < b->nprob; ++p) order[p] = p;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int c) { return b->grids[a].nx * (int64_t)b->grids[a].ny > b->grids[c].nx * (int64_t)b->grids[c].ny; });
+  std::vector<int> order(nprob);
+  for (int p = 0; p < nprob; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return grids[a].nx * (int64_t)grids[a].ny > grids[c].nx * (int64_t)grids[c].ny;
+  });
   std::vector<WorkItem> items2;
-  const int wpb = b->block_x / 64;
+  const int wpb = block_x / 64;
   for (int p : order) {
-    const int ns = (b->grids[p].nx + b->block_x - 1) / b->block_x;
+    const int ns = (grids[p].nx + block_x - 1) / block_x;
     for (int s = 0; s < ns; ++s) items.push_back({p, s});
-    const int ns2 = ((b->grids[p].nx + 59) / 60 + wpb - 1) / wpb;
+    const int ns2 = ((grids[p].nx + 59) / 60 + wpb - 1) / wpb;
     for (int s = 0; s < ns2; ++s) items2.push_back({p, s});
   }
   // The hardware deals block ids round-robin to the 8 XCDs. Within each span of
@@ -2039,6 +2060,13 @@ static lb_status batch_items(lb_batch* b) {
     }
     items2.swap(dealt);
   }
+  items_out->swap(items);
+  items2_out->swap(items2);
+}
+
+static lb_status batch_items(lb_batch* b) {
+  std::vector<WorkItem> items, items2;
+  lbkt_plan_batch(b->grids.data(), b->nprob, b->block_x, &items, &items2);
   if (b->d_items) HIP_CHECK(hipFree(b->d_items));
   if (b->d_items2) HIP_CHECK(hipFree(b->d_items2));
   b->d_items = b->d_items2 = nullptr;
@@ -2058,12 +2086,13 @@ static int batch_default_steps(const lb_batch* b) {
   return 2;
 }
 
-extern "C" lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, lb_prec prec, lb_batch** out) {
+extern "C" lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, int32_t prec_code, lb_batch** out) {
   if (!out) return fail(LB_EINVAL, "out is NULL");
   *out = nullptr;
   if (nprob < 1 || !grids) return fail(LB_EINVAL, "need nprob >= 1 grids");
   lb_status s;
-  if ((s = check_prec(prec))) return s;
+  if ((s = check_prec(prec_code))) return s;
+  const lb_prec prec = (lb_prec)prec_code;
   lb_batch* b = new (std::nothrow) lb_batch();
   if (!b) return fail(LB_ENOMEM, "batch allocation failed");
   b->nprob = nprob;
@@ -2241,8 +2270,10 @@ extern "C" void lb_batch_destroy(lb_batch* b) {
 
 // ------------------------------------------------------------------ autotuner
 
-extern "C" lb_status lb_autotune(const lb_grid* g, lb_prec prec, void* fa, void* fb, int32_t reps, lb_tile* best,
+extern "C" lb_status lb_autotune(const lb_grid* g, int32_t prec_code, void* fa, void* fb, int32_t reps, lb_tile* best,
                                  float* best_ms, void* stream) {
+  if (check_prec(prec_code)) return LB_EINVAL;
+  const lb_prec prec = (lb_prec)prec_code;
   lb_status s;
   if ((s = lb_validate(g)) || (s = check_prec(prec)) || (s = check_ptr(fa, "f_a")) || (s = check_ptr(fb, "f_b")))
     return s;
@@ -2345,7 +2376,7 @@ extern "C" int64_t lb_struct_size(int32_t which) {
   return -1;
 }
 
-extern "C" const char* lb_status_str(lb_status s) {
+extern "C" const char* lb_status_str(int32_t s) {
   switch (s) {
     case LB_OK: return "LB_OK";
     case LB_EINVAL: return "LB_EINVAL";

@@ -44,10 +44,11 @@ static lb_status scratch_ptr(double** out) {
   return LB_OK;
 }
 
-extern "C" lb_status lb_invariants_noalloc(const lb_grid* g, lb_prec prec, const void* f, double* out4,
+extern "C" lb_status lb_invariants_noalloc(const lb_grid* g, int32_t prec_code, const void* f, double* out4,
                                            void* stream) {
   lb_status s;
-  if ((s = lbkt_invariants_args(g, prec, f, out4))) return s;
+  if ((s = lbkt_invariants_args(g, prec_code, f, out4))) return s;
+  const lb_prec prec = (lb_prec)prec_code;
   int rpb, nb;
   lbkt_inv_partition(g, &rpb, &nb);
   if (nb > kScratchParts) {

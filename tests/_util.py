@@ -49,20 +49,22 @@ def rel_l1(a, b):
 
 @functools.lru_cache(maxsize=16)
 def _oracle_cached(key):
-    cfg, nsteps = _CFG_REGISTRY[key]
+    cfg, nsteps, storage = _CFG_REGISTRY[key]
     pb = scheme.Problem.from_dict(cfg)
-    f = scheme.init(pb, *P.init_fields(cfg))
-    f = scheme.run(pb, f, nsteps)
+    f = scheme.store(scheme.init(pb, *P.init_fields(cfg)), storage)
+    f = scheme.run(pb, f, nsteps, storage=storage)
     return scheme.fields(pb, f), f
 
 
 _CFG_REGISTRY = {}
 
 
-def oracle_run(name, cfg, nsteps):
-    """Oracle fields after nsteps from the workload's initial fields (cached per name)."""
-    _CFG_REGISTRY[name] = (cfg, nsteps)
-    return _oracle_cached(name)
+def oracle_run(name, cfg, nsteps, storage=None):
+    """Oracle fields after nsteps from the workload's initial fields (cached per name);
+    storage=torch.float32: every stored state rounded to float32 (FP32 storage)."""
+    key = name if storage is None else name + "|" + str(storage)
+    _CFG_REGISTRY[key] = (cfg, nsteps, storage)
+    return _oracle_cached(key)
 
 
 def gpu_run(cfg, nsteps, prec="f64", tile=None, use_graph=False, fields=None):

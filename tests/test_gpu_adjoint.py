@@ -168,43 +168,96 @@ def test_keeping_every_state_gives_the_same_gradient(prec):
     assert torch.equal(got, ref)
 
 
+def _oracle_tape_gradient(cfg, fields, tgt, steps, storage=None):
+    """Reverse-mode autograd through the oracle (init, steps, density, loss); with
+    storage=float32 every stored state is rounded to float32 on the way forward and
+    the rounding is the identity on the way back (as the library's adjoint treats it)."""
+    pb = scheme.Problem.from_dict(cfg)
+    r0 = torch.tensor(fields[0], dtype=F64, requires_grad=True)
+    u, v, p = [torch.tensor(a, dtype=F64) for a in fields[1:]]
+
+    def st(f):
+        return f if storage is None else f + (scheme.store(f.detach(), storage) - f.detach())
+
+    f = st(scheme.init(pb, r0, u, v, p))
+    for n in range(steps):
+        f = st(scheme.step(pb, f, n))
+    rho = scheme.fields(pb, f)[0]
+    L = ((rho - tgt) ** 2).sum()
+    L.backward()
+    return float(L.detach()), r0.grad
+
+
+def test_fp32_storage_rollout_gradient_matches_oracle_tape():
+    """The 48 x 12 double-Mach problem in FP32 storage: the GPU gradient (FP32 f, FP64
+    adjoint, sqrt(N) checkpoints) against the oracle's tape of the same FP32-storage
+    forward, element by element within 1e-10 of the largest component."""
+    steps = 60
+    cfg, fields, target = _dmr_problem(48, 12, steps)
+    R, loss, grad, tgt = _gpu_gradient(cfg, fields, target, "f32")
+    L, want = _oracle_tape_gradient(cfg, fields, tgt.cpu(), steps, storage=torch.float32)
+    err = float((grad.cpu() - want).abs().max() / want.abs().max())
+    say("fp32 tape err", err, "loss", float(loss), L)
+    assert abs(float(loss) - L) <= 1e-10 * L
+    assert err < 1e-10
+
+
 def test_rollout_gradient_central_differences_on_full_grid():
     """960 x 240 double-Mach problem, 2000 steps, FP64: the adjoint gradient against
-    central differences (eps = 1e-4 rho: truncation ~1e-8, rounding noise ~1e-8 relative)
-    at cells of the 48 x 12 window at the wall start."""
+    central differences (eps = 1e-4 rho: truncation ~1e-8 relative) at every cell of the
+    48 x 12 crop at the wall start (576 cells, 1152 forward runs). Bar per cell:
+    |fd - g| <= 1e-6 max(|g|, 1e-3 max|g|)."""
     lb = _lb()
     cfg, fields, target = _dmr_problem(960, 240, 2000)
     R, loss, grad, tgt = _gpu_gradient(cfg, fields, target, "f64")
     g = R.g
     rho, ux, uy, p = [torch.tensor(np.ascontiguousarray(a), dtype=F64, device=DEV) for a in fields]
     x0 = int(round(cfg["x0"] / cfg["dx"]))
-    rng = np.random.default_rng(9)
-    cells = [(int(rng.integers(0, 12)), x0 + int(rng.integers(0, 48))) for _ in range(12)]
     fa = lb.empty(g, "f64", DEV)
     fb = lb.empty(g, "f64", DEV)
 
     def loss_at(r):
         lb.init(g, r, ux, uy, p, out=fa)
-        out = lb.run(g, fa, fb, cfg["steps"])
+        out = lb.run(g, fa, fb, cfg["steps"], use_graph=True)
         rN = lb.moments(g, out, flags=False)[0]
         return float(((rN - tgt) ** 2).sum())
 
     scale = float(grad.abs().max())
-    for (y, x) in cells:
-        eps = 1e-4 * float(rho[y, x])
-        rp = rho.clone()
-        rp[y, x] += eps
-        rm = rho.clone()
-        rm[y, x] -= eps
-        fd = (loss_at(rp) - loss_at(rm)) / (2 * eps)
-        say("cell", y, x, "fd", fd, "adj", float(grad[y, x]))
-        assert abs(fd - float(grad[y, x])) <= 1e-6 * max(abs(fd), 1e-3 * scale)
+    grad_c = grad.cpu()
+    worst, bad = 0.0, []
+    rp = rho.clone()
+    for y in range(12):
+        for x in range(x0, x0 + 48):
+            eps = 1e-4 * float(rho[y, x])
+            rp[y, x] = rho[y, x] + eps
+            lp = loss_at(rp)
+            rp[y, x] = rho[y, x] - eps
+            lm = loss_at(rp)
+            rp[y, x] = rho[y, x]
+            fd = (lp - lm) / (2 * eps)
+            ad = float(grad_c[y, x])
+            tol = 1e-6 * max(abs(ad), 1e-3 * scale)
+            worst = max(worst, abs(fd - ad) / tol)
+            if abs(fd - ad) > tol:
+                bad.append((y, x, fd, ad))
+    say("central differences over 576 cells: worst |fd - g| / bar", worst, "failing", len(bad), bad[:5])
+    assert not bad
 
 
 def test_fp32_storage_gradient_close_to_fp64():
+    """The 960 x 240 double-Mach gradient (2000 steps) in FP32 storage against FP64
+    storage, element by element: |g32 - g64| <= 2e-3 max|g64| at every cell and
+    relative L2 <= 1e-3 (FP32 rounding of the 2000 stored states perturbs the
+    trajectory the adjoint runs along)."""
     cfg, fields, target = _dmr_problem(960, 240, 2000)
     _, _, g64, tgt = _gpu_gradient(cfg, fields, target, "f64")
     _, _, g32, _ = _gpu_gradient(cfg, fields, target, "f32")
+    scale = float(g64.abs().max())
+    d = (g32 - g64).abs()
     rel = float((g32 - g64).norm() / g64.norm())
-    say("fp32 vs fp64 gradient rel L2", rel)
+    big = g64.abs() > 0.1 * scale
+    say("fp32 vs fp64 gradient: rel L2", rel, "max |diff| / max|g64|", float(d.max()) / scale,
+        "max relative diff where |g64| > 0.1 max", float((d[big] / g64.abs()[big]).max()),
+        "cells above 1e-3 max:", int((d > 1e-3 * scale).sum()))
+    assert float(d.max()) <= 2e-3 * scale
     assert rel < 1e-3

@@ -65,6 +65,52 @@ def test_fp32_storage_l1_bound(name, bound):
     assert e <= bound
 
 
+# ------------------------------------------------------------------ long runs (Sec. 4.2)
+
+LONG = {
+    # regular reflection (Sec. 4.2 at Mach 2.9, Eq. (Riemann-3) states): 4000 of its ~20000 steps
+    "regular_reflection_4000": (P.regular_reflection(steps=4000), 4000),
+    # double Mach reflection (Sec. 4.2, Fig. 12): the whole 2000-step run of the gradient workload
+    "double_mach_2000": (P.double_mach(steps=2000), 2000),
+    # the paper-resolution Mach-10 regular reflection (Fig. 11: 900 x 300, c = (10, 20, 15)) at
+    # the scanner's alpha = 0.1: its first 200 steps
+    "regular_reflection_mach10_900x300": (P.regular_reflection_paper(alpha=0.1), 200),
+}
+
+
+@pytest.mark.parametrize("name", ["regular_reflection_4000", "double_mach_2000"])
+def test_long_runs_fp64_match_oracle(name):
+    """The long runs in FP64 storage: rho, u, T within 1e-12 of the FP64 oracle."""
+    cfg, n = LONG[name]
+    say("case long fp64", name, cfg["nx"], cfg["ny"], n)
+    g, f = gpu_run(cfg, n, "f64")
+    got, flags = gpu_fields(g, f, "f64")
+    assert int(flags[0]) & 3 == 0
+    want, _ = oracle_run(name, cfg, n)
+    say(name, "fp64 errors", compare_fields(got, want, 1e-12))
+
+
+@pytest.mark.parametrize("name", list(LONG))
+def test_long_runs_fp32_storage(name):
+    """The long runs in FP32 storage (float32 values, float64 arithmetic): relative
+    L1(rho) <= 1e-9 against the oracle run with the same storage rounding (the kernel
+    computes exactly the FP32-storage scheme), and against the FP64 oracle within the
+    storage error the oracle itself shows plus 1e-9, at most 1e-6."""
+    cfg, n = LONG[name]
+    say("case long fp32", name, cfg["nx"], cfg["ny"], n)
+    g, f = gpu_run(cfg, n, "f32")
+    got, flags = gpu_fields(g, f, "f32")
+    assert int(flags[0]) & 3 == 0
+    w32, _ = oracle_run(name, cfg, n, storage=torch.float32)
+    w64, _ = oracle_run(name, cfg, n)
+    e32 = rel_l1(got[0], w32[0])
+    e64 = rel_l1(got[0], w64[0])
+    own = rel_l1(w32[0], w64[0])
+    say(name, "fp32: vs fp32-storage oracle", e32, "vs fp64 oracle", e64, "oracle's own storage error", own)
+    assert e32 <= 1e-9
+    assert e64 <= own + 1e-9 and e64 <= 1e-6
+
+
 # ------------------------------------------------------------------ boundary matrix, ragged sizes
 
 def _edge(kind, **kw):

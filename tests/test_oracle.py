@@ -11,6 +11,7 @@ import math
 import os
 
 import mpmath
+import numpy as np
 
 import pytest
 import torch
@@ -414,3 +415,152 @@ def test_shock_edge_behind_and_ahead():
     for i in range(pb.nx):
         want = fa if i < pb.edges[2].split else f[perm, 0, i]
         assert torch.equal(F[:, 0, i + 1], want)
+
+
+# ------------------------------------------------------------------ moving-shock edge against the interior shock
+
+def _free_shock_problem(nx=72, ny=24):
+    """The double-Mach shock (Mach 10 at 60 degrees into (1.4, 0, 0, 1), Sec. 4.2) with no
+    wall: both y edges are the moving-shock edge, so the exact solution is the initial
+    planar shock translated along its normal."""
+    cfg = P.double_mach(nx=nx, ny=ny, length=nx * 0.01, wall_cells=10, alpha=0.1)
+    top = cfg["edges"][3]
+    cfg["edges"] = [cfg["edges"][0], cfg["edges"][1], dict(top), dict(top)]
+    return cfg
+
+
+def _equal_area_positions(rho, pre, post, k0, dx):
+    """Per row, the x where a sharp jump from post to pre would hold the same mass as
+    the row right of face k0 (behind the shock the row is at the post-shock state)."""
+    return (k0 + (rho[:, k0:] - pre).sum(1) / (post - pre)) * dx
+
+
+def _ghost_transition(pb, f, name, t, pre, post):
+    """x of the cell face where the ghost row of edge `name` switches from the
+    post-shock to the pre-shock equilibrium (its density, Eq. (e4))."""
+    r = scheme._ghost_line(pb, f, name, t).sum(0)
+    k = torch.nonzero(r > 0.5 * (pre + post)).max()
+    return (int(k) + 1) * pb.dx
+
+
+def _shock_pin(cfg, plant=None):
+    """Run the oracle until the shock has moved 25 cells; return the measured
+    deviations of the interior shock from planar-shock physics and of the ghost
+    transitions from the interior shock line. plant = (field, fn) changes that
+    parameter of the two shock ghost edges only (a planted mistake)."""
+    pre, post = cfg["pre"], cfg["post"]
+    pb = scheme.Problem.from_dict(cfg)
+    if plant:
+        for e in pb.edges[2:]:
+            setattr(e, plant[0], plant[1](getattr(e, plant[0])))
+    fields = P.init_fields(cfg)
+    nx, ny, dx = pb.nx, pb.ny, pb.dx
+    slope = 1.0 / math.tan(math.radians(60.0))           # x per unit y along the incident shock
+    # Rankine-Hugoniot: the shock speed along its normal n (towards the gas at rest) is the
+    # jump of the mass flux over the jump of the density
+    n = torch.tensor([1.0, -slope], dtype=torch.float64) / math.sqrt(1.0 + slope * slope)
+    un_post = post[1] * float(n[0]) + post[2] * float(n[1])
+    un_pre = pre[1] * float(n[0]) + pre[2] * float(n[1])
+    speed = (post[0] * un_post - pre[0] * un_pre) / (post[0] - pre[0])
+    shift = 25.0 * dx                                      # x displacement to run for
+    nsteps = int(round(shift / (speed * pb.dt * math.sqrt(1.0 + slope * slope))))
+    y = (torch.arange(ny, dtype=torch.float64) + 0.5) * dx
+    x_init = _equal_area_positions(torch.as_tensor(fields[0]), pre[0], post[0], 4, dx)
+    f = scheme.init(pb, *fields)
+    for k in range(nsteps):
+        f = scheme.step(pb, f, k)
+    t = nsteps * pb.dt
+    x_end = _equal_area_positions(scheme.fields(pb, f)[0], pre[0], post[0], 4, dx)
+    inner = slice(2, ny - 2)                               # rows clear of the ghost rows' own stencil
+    A = torch.stack([torch.ones(ny, dtype=torch.float64), y], 1)[inner]
+    a0 = float(torch.linalg.lstsq(A, x_init[inner].unsqueeze(1)).solution[0])
+    a1, b1 = [float(v) for v in torch.linalg.lstsq(A, x_end[inner].unsqueeze(1)).solution[:, 0]]
+    resid = float((x_end[inner] - (a1 + b1 * y[inner])).abs().max()) / dx
+    moved = (a1 - a0) / dx
+    want = speed * t * math.sqrt(1.0 + slope * slope) / dx
+    gb = _ghost_transition(pb, f, "y-", t, pre[0], post[0])
+    gt = _ghost_transition(pb, f, "y+", t, pre[0], post[0])
+    dev_b = (gb - (a1 + b1 * (-0.5 * dx))) / dx
+    dev_t = (gt - (a1 + b1 * ((ny + 0.5) * dx))) / dx
+    return {"speed": speed, "moved": moved, "want": want, "slope_err": abs(b1 - slope), "resid": resid,
+            "ghost_dev": max(abs(dev_b), abs(dev_t))}
+
+
+def _shock_pin_holds(d):
+    """Planar-shock physics in the interior and ghosts on the interior shock line:
+    straight (0.3 cell), at the initial 60 degrees (slope within 0.012), moved by the
+    Rankine-Hugoniot speed times t (0.3 cell), ghost transitions within 0.6 cell of
+    the line extended to the ghost rows."""
+    return d["resid"] <= 0.3 and d["slope_err"] <= 0.012 and abs(d["moved"] - d["want"]) <= 0.3 \
+        and d["ghost_dev"] <= 0.6
+
+
+def test_moving_shock_edge_moves_with_the_interior_shock():
+    """The moving-shock ghost rows, checked against the dynamics instead of their
+    formula: on a domain whose y edges are both moving-shock edges, the interior shock
+    (equal-area position per row, which a conservative scheme moves at the
+    Rankine-Hugoniot speed) must stay planar at 60 degrees, move by the speed the
+    mass-flux jump of the two states gives, and pass through the ghost rows' transitions."""
+    nthreads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        d = _shock_pin(_free_shock_problem())
+    finally:
+        torch.set_num_threads(nthreads)
+    assert abs(d["speed"] - 10.0) < 1e-9          # the states are a Mach-10 shock
+    assert d["want"] > 24.0
+    assert _shock_pin_holds(d), d
+
+
+@pytest.mark.parametrize("plant", [("speed", 0.9), ("speed", 1.05), ("angle_deg", -3.0), ("angle_deg", 1.0),
+                                   ("x0", 0.02), ("x0", -0.01)], ids=lambda p: "%s%+g" % p)
+def test_moving_shock_pin_catches_planted_ghost_mistakes(plant):
+    """The pin above fails when the ghost rows alone are moved: a speed off by 5-10%,
+    the angle off by 1-3 degrees, the origin off by one or two cells."""
+    field, v = plant
+    fn = (lambda s: s * v) if field == "speed" else (lambda s: s + v)
+    nthreads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        d = _shock_pin(_free_shock_problem(), (field, fn))
+    finally:
+        torch.set_num_threads(nthreads)
+    assert not _shock_pin_holds(d), d
+
+
+def test_amplification_over_many_wave_vectors_equals_the_single_form():
+    """The vectorised G(k) equals the per-wave-vector G of Eqs. (SEC-VON-8), (SEC-VON-9),
+    (SEC-VON-12) (pinned above against the step's linearisation) at random states,
+    parameters and wave vectors, bitwise; its largest radius too."""
+    rng = np.random.default_rng(11)
+    for _ in range(5):
+        c1 = float(rng.uniform(1, 10))
+        p = vn.figure_params(c1=c1, c2=c1 * float(rng.uniform(1.5, 3)), eta0=c1 * float(rng.uniform(1, 2)),
+                             alpha=float(rng.uniform(0.05, 0.4)), beta=float(rng.uniform(0, 0.5)),
+                             tau=float(rng.uniform(0.8, 2)))
+        st = (float(rng.uniform(0.5, 2)), float(rng.uniform(-c1, c1)), float(rng.uniform(-c1, c1) / 3),
+              float(rng.uniform(0.2, 1) * c1 * c1 / 4))
+        kx = rng.uniform(-math.pi, math.pi, 7).tolist()
+        ky = rng.uniform(-math.pi, math.pi, 7).tolist()
+        G = vn.amplification_many(st, p, kx, ky)
+        for q in range(7):
+            assert torch.equal(G[q], vn.amplification(st, p, kx[q], ky[q]))
+        assert vn.max_modulus_many(st, p, kx, ky) == max(vn.max_modulus(st, p, a, b) for a, b in zip(kx, ky))
+
+
+def test_fp32_storage_run_rounds_each_stored_state():
+    """scheme.run with float32 storage equals FP64 steps with each result rounded to the
+    nearest float32 (round-to-nearest is exact in float64 and idempotent), and differs
+    from the FP64 run by about the float32 rounding."""
+    cfg = P.periodic_smooth(nx=20, ny=8, steps=5)
+    pb = scheme.Problem.from_dict(cfg)
+    f0 = scheme.store(scheme.init(pb, *P.init_fields(cfg)), torch.float32)
+    assert torch.equal(scheme.store(f0, torch.float32), f0)
+    f = f0
+    for n in range(5):
+        f = scheme.step(pb, f, n).to(torch.float32).to(torch.float64)
+    got = scheme.run(pb, f0, 5, storage=torch.float32)
+    assert torch.equal(got, f)
+    f64 = scheme.run(pb, f0, 5)
+    rel = float(((got - f64).abs() / f64.abs()).max())
+    assert 0 < rel < 5 * 2.0 ** -24

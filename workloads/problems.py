@@ -339,3 +339,29 @@ def batched(nprob=256, seed=0, steps=2000, alpha=0.025, ny=4, screen=True, max_a
         else:
             raise RuntimeError("slot %d: no accepted draw in %d attempts" % (p, max_attempts))
     return out, {"vacuum_redraws": vac, "unstable_redraws": unstable, "screened": rejected is not None}
+
+
+# ------------------------------------------------------------------ von Neumann chooser inputs (batched draws)
+
+# Candidate alpha = c2 dt / dx, ascending, and the growth tolerance of the chooser: a
+# mode may grow by at most a factor 2 over a 2000-step run (radius <= 1 + ln 2 / 2000).
+VN_ALPHAS = (0.025, 0.05, 0.075, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0.4, 0.45, 0.5)
+VN_TOL = math.log(2.0) / 2000
+
+
+def vn_wave_vectors(nkx=64):
+    """(kdx, kdy) lists: nkx values of k_x dx on [0, 2 pi) times the 4 modes k_y dy of a
+    4-row periodic grid (0, pi/2, pi, 3 pi/2)."""
+    kx = [k * (2 * math.pi / nkx) for k in range(nkx) for _ in range(4)]
+    ky = [j * (math.pi / 2) for _ in range(nkx) for j in range(4)]
+    return kx, ky
+
+
+def batched_vn_states(cfg):
+    """The uniform states (rho, ux, uy, T) whose linear stability bounds a batched
+    Riemann problem's time step: its left and right states and the two exact star
+    states between them."""
+    L, R = cfg["left"], cfg["right"]
+    st = gasdyn.riemann_star(cfg["gamma"], (L[0], L[1], L[3]), (R[0], R[1], R[3]))
+    return [(L[0], L[1], 0.0, L[3] / L[0]), (R[0], R[1], 0.0, R[3] / R[0]),
+            (st.rho_l, st.u, 0.0, st.p / st.rho_l), (st.rho_r, st.u, 0.0, st.p / st.rho_r)]
