@@ -203,10 +203,13 @@ def test_fp32_storage_rollout_gradient_matches_oracle_tape():
 
 
 def test_rollout_gradient_central_differences_on_full_grid():
-    """960 x 240 double-Mach problem, 2000 steps, FP64: the adjoint gradient against
-    central differences (eps = 1e-4 rho: truncation ~1e-8 relative) at every cell of the
-    48 x 12 crop at the wall start (576 cells, 1152 forward runs). Bar per cell:
-    |fd - g| <= 1e-6 max(|g|, 1e-3 max|g|)."""
+    """960 x 240 double-Mach problem, 2000 steps, FP64: the adjoint gradient g against
+    central differences d(eps) at every cell of the 48 x 12 crop at the wall start (576
+    cells, central differences at eps = 1e-4 rho and eps/2: 2304 forward runs). The
+    error of d(eps) is truncation (O(eps^2), about 4/3 of d(eps) - d(eps/2)) plus the
+    rounding noise of the loss difference (about 1e-6 of g here: the two perturbed
+    2000-step trajectories round differently), which d(eps) - d(eps/2) also measures.
+    Bar per cell: |d(eps) - g| <= 1e-6 max(|g|, 1e-3 max|g|) + 2 |d(eps) - d(eps/2)|."""
     lb = _lb()
     cfg, fields, target = _dmr_problem(960, 240, 2000)
     R, loss, grad, tgt = _gpu_gradient(cfg, fields, target, "f64")
@@ -224,23 +227,32 @@ def test_rollout_gradient_central_differences_on_full_grid():
 
     scale = float(grad.abs().max())
     grad_c = grad.cpu()
-    worst, bad = 0.0, []
     rp = rho.clone()
+
+    def central(y, x, eps):
+        rp[y, x] = rho[y, x] + eps
+        lp = loss_at(rp)
+        rp[y, x] = rho[y, x] - eps
+        lm = loss_at(rp)
+        rp[y, x] = rho[y, x]
+        return (lp - lm) / (2 * eps)
+
+    worst, worst_rel, spread_used, bad = 0.0, 0.0, 0, []
     for y in range(12):
         for x in range(x0, x0 + 48):
             eps = 1e-4 * float(rho[y, x])
-            rp[y, x] = rho[y, x] + eps
-            lp = loss_at(rp)
-            rp[y, x] = rho[y, x] - eps
-            lm = loss_at(rp)
-            rp[y, x] = rho[y, x]
-            fd = (lp - lm) / (2 * eps)
+            d1 = central(y, x, eps)
+            d2 = central(y, x, 0.5 * eps)
             ad = float(grad_c[y, x])
-            tol = 1e-6 * max(abs(ad), 1e-3 * scale)
-            worst = max(worst, abs(fd - ad) / tol)
-            if abs(fd - ad) > tol:
-                bad.append((y, x, fd, ad))
-    say("central differences over 576 cells: worst |fd - g| / bar", worst, "failing", len(bad), bad[:5])
+            base = 1e-6 * max(abs(ad), 1e-3 * scale)
+            tol = base + 2.0 * abs(d1 - d2)
+            worst = max(worst, abs(d1 - ad) / tol)
+            worst_rel = max(worst_rel, abs(d1 - ad) / max(abs(ad), 1e-3 * scale))
+            spread_used += int(abs(d1 - ad) > base)
+            if abs(d1 - ad) > tol:
+                bad.append((y, x, d1, d2, ad))
+    say("central differences over 576 cells: worst |d - g| / bar", worst, "worst relative |d - g|", worst_rel,
+        "cells beyond 1e-6 relative (within the step-size spread):", spread_used, "failing", len(bad), bad[:5])
     assert not bad
 
 
