@@ -289,44 +289,38 @@ def bench_adjoint_step(dev, fwd_ms, nsteps=20):
             "finite": finite}
 
 
-VN_ALPHAS = (0.025, 0.05, 0.075, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0.4, 0.45, 0.5)
-
-
-def vn_cases(alphas=VN_ALPHAS, nkx=64):
-    """The scanner's inputs for the 256 batched Riemann problems: for each problem's
-    left, right and two star states a case, its candidate time steps (alpha dx / c2)
-    and its problem index, and the 64 x 4 wave vectors of a 4-row periodic grid."""
-    import math as m
+def vn_cases():
+    """The chooser's inputs for the 256 batched Riemann problems (as in the oracle's
+    reference): each problem's left, right and two star states as cases, the candidate
+    time steps alpha dx / c2, the owning problem, and the 64 x 4 wave vectors of a
+    4-row periodic grid."""
     from paper_0706_0405_amd import vn
     import paper_0706_0405_amd as lb
-    from workloads import gasdyn, problems as P
+    from workloads import problems as P
 
     cfgs, _ = P.batched()
     cases, dts, owner = [], [], []
     for k, c in enumerate(cfgs):
         g = lb.Grid.from_workload(c)
-        L, R = c["left"], c["right"]
-        st = gasdyn.riemann_star(g.gamma, (L[0], L[1], L[3]), (R[0], R[1], R[3]))
-        for s in ((L[0], L[1], 0.0, L[3] / L[0]), (R[0], R[1], 0.0, R[3] / R[0]),
-                  (st.rho_l, st.u, 0.0, st.p / st.rho_l), (st.rho_r, st.u, 0.0, st.p / st.rho_r)):
-            cases.append(vn.case(g, s))
-            dts.append([a * g.dx / g.c2 for a in alphas])
+        for st in P.batched_vn_states(c):
+            cases.append(vn.case(g, st))
+            dts.append([a * g.dx / g.c2 for a in P.VN_ALPHAS])
             owner.append(k)
-    kx = [k * (2 * m.pi / nkx) for k in range(nkx) for _ in range(4)]
-    ky = [j * (m.pi / 2) for _ in range(nkx) for j in range(4)]
+    kx, ky = P.vn_wave_vectors()
     return cfgs, cases, dts, owner, kx, ky
 
 
-def bench_vn(dev, alphas=VN_ALPHAS, nkx=64):
+def bench_vn(dev):
     """GPU von Neumann chooser on the 256 batched Riemann problems: for each problem's
     left, right and two star states, the largest stable alpha = dt c2 / dx among the
     candidates over 64 x 4 wave vectors of its periodic grid, the problem taking the
-    minimum over its states."""
-    import math as m
+    minimum over its states; with the strict bound (radius <= 1 + 1e-9) and with the
+    growth bound of the workload (a mode may grow 2x over 2000 steps)."""
     import torch
     from paper_0706_0405_amd import vn
+    from workloads import problems as P
 
-    cfgs, cases, dts, owner, kxl, kyl = vn_cases(alphas, nkx)
+    cfgs, cases, dts, owner, kxl, kyl = vn_cases()
     kx = torch.tensor(kxl, dtype=torch.float64, device=dev)
     ky = torch.tensor(kyl, dtype=torch.float64, device=dev)
     vn.max_stable_dt(cases, dts, kx, ky, 1e-9)        # warm (module load, first launch)
@@ -334,10 +328,8 @@ def bench_vn(dev, alphas=VN_ALPHAS, nkx=64):
     t0 = time.perf_counter()
     best = vn.max_stable_dt(cases, dts, kx, ky, 1e-9)
     t = time.perf_counter() - t0
-    points = len(cases) * len(alphas) * kx.numel()
-    # tolerances: strict (radius <= 1 + 1e-9), and linear growth of at most 2x over the 2000-step run
-    tol_run = m.log(2.0) / 2000
-    best_run = vn.max_stable_dt(cases, dts, kx, ky, tol_run)
+    points = len(cases) * len(P.VN_ALPHAS) * kx.numel()
+    best_run = vn.max_stable_dt(cases, dts, kx, ky, P.VN_TOL)
 
     def per_problem(b):
         per = {}
@@ -345,11 +337,14 @@ def bench_vn(dev, alphas=VN_ALPHAS, nkx=64):
             a = dt * c.c2 / c.dx
             per[k] = min(per.get(k, a), a)
         v = sorted(per.values())
-        return {"min": v[0], "median": v[len(v) // 2], "max": v[-1], "at_least_0.1": sum(a >= 0.1 for a in v)}
-    return {"problems": len(cfgs), "states_per_problem": 4, "alphas": list(alphas), "wave_vectors": kx.numel(),
+        return per, {"min": v[0], "median": v[len(v) // 2], "max": v[-1], "at_least_0.1": sum(a >= 0.1 for a in v)}
+    _, strict = per_problem(best)
+    per_run, growth = per_problem(best_run)
+    ratio = max(c["dt"] * c["c2"] / c["dx"] / per_run[k] for k, c in enumerate(cfgs))
+    return {"problems": len(cfgs), "states_per_problem": 4, "alphas": list(P.VN_ALPHAS), "wave_vectors": kx.numel(),
             "points": points, "ms": t * 1e3, "points_per_s": points / t,
-            "chosen_alpha_strict": per_problem(best), "tol_run": tol_run,
-            "chosen_alpha_growth_2x_over_run": per_problem(best_run)}
+            "chosen_alpha_strict": strict, "tol_run": P.VN_TOL, "chosen_alpha_growth_2x_over_run": growth,
+            "workload_alpha_over_chosen_max": ratio}
 
 
 def bench_configs(dev, max_steps=4000):

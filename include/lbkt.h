@@ -257,9 +257,20 @@ lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, int32_t prec, lb_
  * the pitch written to pitches[p] (host int64[nprob], may be NULL). */
 lb_status lb_batch_layout(const lb_batch* b, int64_t* offsets, int64_t* pitches, int64_t* total);
 
-/* Set the launch shape of the batched step (block_x threads per work item;
- * rows and blocks are ignored: a work item covers all rows of its problem;
- * steps: time steps per pass, 0 = the default, 1 or 2). */
+/* Set the launch shape of the batched step: block_x threads per work item (a
+ * work item covers all rows of a strip of its problem); steps: time steps per
+ * pass, 0 = the default, 1 or 2. blocks = 0: one launch per two-step pass (the
+ * default). blocks > 0: all two-step passes of a call in ONE launch of at most
+ * `blocks` co-resident blocks (fewer if fewer fit on the device at once), each
+ * block taking its share of the work items pass after pass and waiting, before
+ * each pass of an item, until the items whose columns it reads have finished the
+ * previous pass (progress counters with release/acquire atomics); results are
+ * bitwise those of the per-pass launches. rows (persistent launch only): polls
+ * per wait before a block gives up (0 = the default, 2^20); a block that gives up
+ * flags the batch and ends, and so do the others at their next wait, so the launch
+ * always terminates, with an incomplete result that lb_batch_status reports. Other
+ * work on the device that keeps blocks of the launch from being resident can make
+ * it give up. LB_EINVAL for a bad width, steps, or negative blocks or rows. */
 lb_status lb_batch_set_tile(lb_batch* b, const lb_tile* tile);
 
 /* nsteps steps of every problem, all problems per launch, the launches captured
@@ -269,6 +280,12 @@ lb_status lb_batch_set_tile(lb_batch* b, const lb_tile* tile);
  * Result in f_a when nsteps is even, else f_b. step index starts at 0 on the
  * first call and continues across calls. */
 lb_status lb_step_batched(lb_batch* b, void* f_a, void* f_b, int32_t nsteps, void* stream);
+
+/* Status of the persistent launches of a batch since the last call: waits for
+ * `stream`, and returns LB_EHIP (and clears the flag) if a block gave up waiting
+ * for a neighbouring strip, so that some problems did not advance; LB_OK
+ * otherwise. Synchronous. */
+lb_status lb_batch_status(lb_batch* b, void* stream);
 
 void lb_batch_destroy(lb_batch* b);
 

@@ -74,6 +74,7 @@ _SIGS = {
     "lb_batch_layout": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
     "lb_batch_set_tile": (c_int32, [c_void_p, POINTER(LbTile)]),
     "lb_step_batched": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "lb_batch_status": (c_int32, [c_void_p, c_void_p]),
     "lb_batch_destroy": (None, [c_void_p]),
     "lb_autotune": (c_int32, [POINTER(LbGrid), c_int32, c_void_p, c_void_p, c_int32, POINTER(LbTile),
                               POINTER(c_float), c_void_p]),

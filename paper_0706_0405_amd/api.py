@@ -295,9 +295,16 @@ class Batch:
         o = self.offsets[p]
         return buf[o:o + 9 * g.ny * self.pitches[p]].view(9, g.ny, self.pitches[p])
 
-    def set_tile(self, block_x, steps_per_pass=0):
-        """Threads per work item (64, 128, 256) and time steps per pass (0 = default, 1 or 2)."""
-        check(lib().lb_batch_set_tile(self.h, ctypes.byref(LbTile(int(block_x), 0, 0, int(steps_per_pass)))))
+    def set_tile(self, block_x, steps_per_pass=0, persistent_blocks=0, polls=0):
+        """Threads per work item (64, 128, 256) and time steps per pass (0 = default, 1 or 2);
+        persistent_blocks > 0: all two-step passes in one launch of at most that many
+        co-resident blocks (polls: poll budget per wait, 0 = the library's default)."""
+        check(lib().lb_batch_set_tile(self.h, ctypes.byref(LbTile(int(block_x), int(polls), int(persistent_blocks),
+                                                                  int(steps_per_pass)))))
+
+    def status(self, device=None):
+        """Raise LbError if a persistent launch gave up waiting (lb_batch_status, synchronous)."""
+        check(lib().lb_batch_status(self.h, _stream(device)))
 
     def step(self, f_a, f_b, nsteps):
         """nsteps steps of every problem in one graph launch; returns the result buffer."""

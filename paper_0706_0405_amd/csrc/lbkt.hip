@@ -1426,13 +1426,13 @@ __device__ __forceinline__ void march2_ny4(const KTConsts& K, const V& fi, const
   row_second<XEDGE>(K, fo, L, 3, q2, q3, q0);
 }
 
+// One two-step work item of a batch: the strip of block_x / 64 wavefronts (60
+// output columns each) of problem w.prob, all rows. NY4: every problem of the
+// batch has 4 rows and a periodic y axis (an instantiation of its own, so that the
+// general march keeps its register allocation).
 template <typename S, bool NY4>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_step2_batched(
-    const KTConsts* __restrict__ Ks, const ProbInfo* __restrict__ info, const WorkItem* __restrict__ items,
-    const S* fin, S* fout) {
-  // NY4: every problem of the batch has 4 rows and a periodic y axis (a kernel of
-  // its own, so that the general march keeps its register allocation)
-  const WorkItem w = items[blockIdx.x];
+__device__ __forceinline__ void batched2_item(const KTConsts* __restrict__ Ks, const ProbInfo* __restrict__ info,
+                                              const WorkItem w, const S* fin, S* fout) {
   const KTConsts& K = Ks[w.prob];
   const int64_t off = info[w.prob].offset;
   const int lane = threadIdx.x & 63;
@@ -1452,6 +1452,87 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   } else {
     march2<false>(K, fi, fo, L, 0, K.ny, 0, 0, 0, 0, NoRec{});
   }
+}
+
+// One two-step pass of every problem: one block per work item.
+template <typename S, bool NY4>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_step2_batched(
+    const KTConsts* __restrict__ Ks, const ProbInfo* __restrict__ info, const WorkItem* __restrict__ items,
+    const S* fin, S* fout) {
+  batched2_item<S, NY4>(Ks, info, items[blockIdx.x], fin, fout);
+}
+
+// Wait (one thread) until work item `item` has finished `k` passes: poll its
+// progress counter with acquire loads (agent scope: the item's stores made before
+// its release are then visible to this block), at most `limit` times, giving up
+// early when another block of the launch has set the stop word. item < 0:
+// nothing to wait for.
+__device__ __forceinline__ bool wait_progress(const uint32_t* prog, int item, uint32_t k, uint32_t limit,
+                                              const uint32_t* stop) {
+  if (item < 0) return true;
+  for (uint32_t n = 0;; ++n) {
+    if (__hip_atomic_load(prog + item, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= k) return true;
+    if (n >= limit || __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// All npasses two-step passes of every problem in one launch of co-resident
+// blocks. Block b takes work items b, b + gridDim.x, ... for pass 0, then the same
+// items for pass 1, and so on (pass k reads fa and writes fb when k is even, the
+// other way round when odd). An item's wavefronts read two columns beyond its
+// strip on each side, held by the items nbrs[i] (left, right; -1: none), whose
+// owners are blocks nbrs[i] mod gridDim.x. After all its items of pass k a block
+// waits for its wavefronts' stores and publishes prog[b] = k + 1 with a release
+// store (one per block and pass: each release writes back the L2, and per-item
+// releases measured 1.5x slower); before pass k >= 1 of item i it waits until the
+// owners of both neighbours have published k, which orders both the reads of pass
+// k-1's output and the overwriting of pass k-2's output (read by them during pass
+// k-1). No deadlock while every block is resident: the block at the smallest pass
+// always finds the blocks it waits for done with the previous one. A wait that
+// exceeds spin_limit polls sets the launch's stop word prog[nitems] (the other
+// blocks then end at their next wait) and the batch's failure word *failed, and
+// ends its block, so the launch always terminates; the result is then
+// incomplete. prog[0 .. nitems] must be zero at the launch (gridDim.x <= nitems).
+template <typename S, bool NY4>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_step2_batched_persistent(
+    const KTConsts* __restrict__ Ks, const ProbInfo* __restrict__ info, const WorkItem* __restrict__ items,
+    const int2* __restrict__ nbrs, int nitems, S* fa, S* fb, int npasses, uint32_t* prog, uint32_t* failed,
+    uint32_t spin_limit) {
+  __shared__ uint32_t go;
+  uint32_t* stop = prog + nitems;
+  const int G = (int)gridDim.x;
+  for (int k = 0; k < npasses; ++k) {
+    const S* fin = (k & 1) ? fb : fa;
+    S* fout = (k & 1) ? fa : fb;
+    for (int i = blockIdx.x; i < nitems; i += G) {
+      if (k > 0) {
+        if (threadIdx.x == 0) {
+          const int2 nb = nbrs[i];
+          const bool ok = wait_progress(prog, nb.x < 0 ? -1 : nb.x % G, (uint32_t)k, spin_limit, stop) &&
+                          wait_progress(prog, nb.y < 0 ? -1 : nb.y % G, (uint32_t)k, spin_limit, stop);
+          if (!ok) {
+            __hip_atomic_store(stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          go = ok ? 1u : 0u;
+        }
+        __syncthreads();
+        if (go == 0u) return;
+      }
+      batched2_item<S, NY4>(Ks, info, items[i], fin, fout);
+      __syncthreads();   // every wavefront is past its use of `go`
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's stores have completed
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_store(prog + blockIdx.x, (uint32_t)(k + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // ------------------------------------------------------------------ host launch helpers
@@ -2023,7 +2104,17 @@ struct lb_batch {
   int g_bx = 0;
   int g_steps = 0;
   void* g_stream = nullptr;
+  bool g_persist = false;
+  int g_cap = 0;
+  uint32_t g_spin = 0;
   hipEvent_t done = nullptr;   // recorded after each replay (the exec is destroyed after it)
+  // persistent launch (all two-step passes in one launch of co-resident blocks)
+  bool persist = false;
+  int persist_cap = 0;            // at most this many blocks (and no more than are co-resident)
+  uint32_t spin_limit = 1u << 20; // polls per wait before a block gives up
+  int2* d_nbrs = nullptr;         // per two-step item: left and right neighbour item (-1: none)
+  uint32_t* d_prog = nullptr;     // per block of the persistent launch: passes finished; then the stop word
+  uint32_t* d_err = nullptr;      // failure word: set when a wait gave up, cleared by lb_batch_status
 };
 
 void lbkt_plan_batch(const lb_grid* grids, int nprob, int block_x, std::vector<LbktWorkItem>* items_out,
@@ -2064,9 +2155,43 @@ void lbkt_plan_batch(const lb_grid* grids, int nprob, int block_x, std::vector<L
   items2_out->swap(items2);
 }
 
+void lbkt_batch_neighbours(const lb_grid* grids, const std::vector<LbktWorkItem>& items2, int block_x,
+                           std::vector<int>* left, std::vector<int>* right) {
+  const int wpb = block_x / 64;
+  std::map<std::pair<int, int>, int> at;
+  for (size_t i = 0; i < items2.size(); ++i) at[{items2[i].prob, items2[i].strip}] = (int)i;
+  left->assign(items2.size(), -1);
+  right->assign(items2.size(), -1);
+  for (size_t i = 0; i < items2.size(); ++i) {
+    const lb_grid& g = grids[items2[i].prob];
+    const int ns = (int)cdiv(cdiv(g.nx, 60), wpb);
+    const bool perx = g.edge[0].kind == LB_BC_PERIODIC;
+    const int s = items2[i].strip;
+    const int l = s > 0 ? s - 1 : (perx ? ns - 1 : -1);
+    const int r = s + 1 < ns ? s + 1 : (perx ? 0 : -1);
+    if (l >= 0 && l != s) (*left)[i] = at[{items2[i].prob, l}];
+    if (r >= 0 && r != s) (*right)[i] = at[{items2[i].prob, r}];
+  }
+}
+
 static lb_status batch_items(lb_batch* b) {
   std::vector<WorkItem> items, items2;
   lbkt_plan_batch(b->grids.data(), b->nprob, b->block_x, &items, &items2);
+  std::vector<int> left, right;
+  lbkt_batch_neighbours(b->grids.data(), items2, b->block_x, &left, &right);
+  std::vector<int2> nb(items2.size());
+  for (size_t i = 0; i < items2.size(); ++i) nb[i] = make_int2(left[i], right[i]);
+  if (b->d_nbrs) HIP_CHECK(hipFree(b->d_nbrs));
+  if (b->d_prog) HIP_CHECK(hipFree(b->d_prog));
+  b->d_nbrs = nullptr;
+  b->d_prog = nullptr;
+  HIP_CHECK(hipMalloc(&b->d_nbrs, nb.size() * sizeof(int2)));
+  HIP_CHECK(hipMemcpy(b->d_nbrs, nb.data(), nb.size() * sizeof(int2), hipMemcpyHostToDevice));
+  HIP_CHECK(hipMalloc(&b->d_prog, (items2.size() + 1) * sizeof(uint32_t)));   // + the launch's stop word
+  if (!b->d_err) {
+    HIP_CHECK(hipMalloc(&b->d_err, sizeof(uint32_t)));
+    HIP_CHECK(hipMemset(b->d_err, 0, sizeof(uint32_t)));
+  }
   if (b->d_items) HIP_CHECK(hipFree(b->d_items));
   if (b->d_items2) HIP_CHECK(hipFree(b->d_items2));
   b->d_items = b->d_items2 = nullptr;
@@ -2162,7 +2287,11 @@ extern "C" lb_status lb_batch_set_tile(lb_batch* b, const lb_tile* tile) {
   if (bx != 64 && bx != 128 && bx != 256) return fail(LB_EINVAL, "tile block_x must be 64, 128 or 256");
   const int sp = tile ? tile->steps : 0;
   if (sp < 0 || sp > 2) return fail(LB_EINVAL, "tile steps must be 0, 1 or 2");
+  if (tile && (tile->blocks < 0 || tile->rows < 0)) return fail(LB_EINVAL, "tile blocks and rows must be >= 0");
   b->steps = (sp == 1 || batch_default_steps(b) == 1) ? 1 : 2;
+  b->persist = tile && tile->blocks > 0;
+  b->persist_cap = tile ? tile->blocks : 0;
+  b->spin_limit = (tile && tile->rows > 0) ? (uint32_t)tile->rows : (1u << 20);
   if (bx == b->block_x) return LB_OK;
   b->block_x = bx;
   return batch_items(b);
@@ -2193,8 +2322,30 @@ static lb_status launch_batched2(lb_batch* b, const void* fin, void* fout, hipSt
   return LB_OK;
 }
 
+// All `passes` two-step passes from fa (passes even: the result lands in fa) in one
+// launch of co-resident blocks, after clearing the progress counters.
+template <typename S>
+static lb_status launch_batched2_persistent(lb_batch* b, void* fa, void* fb, int passes, hipStream_t st) {
+  auto kern = b->all_ny4 ? k_step2_batched_persistent<S, true> : k_step2_batched_persistent<S, false>;
+  int per_cu = 0, ncu = 0;
+  HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, b->block_x, 0));
+  HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->dev));
+  int64_t g = std::min<int64_t>((int64_t)per_cu * ncu, b->nitems2);
+  if (b->persist_cap > 0) g = std::min<int64_t>(g, b->persist_cap);
+  if (g >= 8) g &= ~(int64_t)7;   // blocks dealt to the 8 XCDs as the items were planned
+  if (g < 1) return fail(LB_EHIP, "no block of the persistent batched kernel fits on a compute unit");
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)cdiv(b->nitems2 + 1, 256)), dim3(256), 0, st, b->d_prog,
+                     b->nitems2 + 1, 0u);
+  HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(kern, dim3((unsigned)g), dim3(b->block_x), 0, st, b->d_consts, b->d_info, b->d_items2,
+                     (const int2*)b->d_nbrs, b->nitems2, (S*)fa, (S*)fb, passes, b->d_prog, b->d_err, b->spin_limit);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
 // nsteps steps of the batch from fa (result in fa when nsteps is even): as
-// launch_steps, an even number of two-step passes after 0..3 single steps.
+// launch_steps, an even number of two-step passes after 0..3 single steps; the
+// passes in one persistent launch when asked for.
 static lb_status batched_steps(lb_batch* b, void* fa, void* fb, int nsteps, hipStream_t st) {
   const int pairs = (b->steps == 2) ? (nsteps / 2) & ~1 : 0;
   const int singles = nsteps - 2 * pairs;
@@ -2202,6 +2353,12 @@ static lb_status batched_steps(lb_batch* b, void* fa, void* fb, int nsteps, hipS
   lb_status s;
   for (int j = 0; j < singles; ++j, ++k)
     if ((s = launch_batched(b, (k % 2 == 0) ? fa : fb, (k % 2 == 0) ? fb : fa, st))) return s;
+  if (b->persist && pairs > 0) {
+    void* a = (k % 2 == 0) ? fa : fb;
+    void* c = (k % 2 == 0) ? fb : fa;
+    return b->prec == LB_F64 ? launch_batched2_persistent<double>(b, a, c, pairs, st)
+                             : launch_batched2_persistent<float>(b, a, c, pairs, st);
+  }
   for (int j = 0; j < pairs; ++j, ++k)
     if ((s = launch_batched2(b, (k % 2 == 0) ? fa : fb, (k % 2 == 0) ? fb : fa, st))) return s;
   return LB_OK;
@@ -2223,7 +2380,8 @@ extern "C" lb_status lb_step_batched(lb_batch* b, void* fa, void* fb, int32_t ns
   }
   if (!b->done) HIP_CHECK(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
   if (!(b->exec && b->g_fa == fa && b->g_fb == fb && b->g_nsteps == nsteps && b->g_bx == b->block_x &&
-        b->g_steps == b->steps && b->g_stream == stream)) {
+        b->g_steps == b->steps && b->g_stream == stream && b->g_persist == b->persist &&
+        b->g_cap == b->persist_cap && b->g_spin == b->spin_limit)) {
     if (b->exec) {
       HIP_CHECK(hipEventSynchronize(b->done));   // its last replay may still run, on any stream
       HIP_CHECK(hipGraphExecDestroy(b->exec));
@@ -2247,6 +2405,9 @@ extern "C" lb_status lb_step_batched(lb_batch* b, void* fa, void* fb, int32_t ns
     b->g_bx = b->block_x;
     b->g_steps = b->steps;
     b->g_stream = stream;
+    b->g_persist = b->persist;
+    b->g_cap = b->persist_cap;
+    b->g_spin = b->spin_limit;
   }
   HIP_CHECK(hipGraphLaunch(b->exec, st));
   HIP_CHECK(hipEventRecord(b->done, st));
@@ -2265,7 +2426,25 @@ extern "C" void lb_batch_destroy(lb_batch* b) {
   if (b->d_info) (void)hipFree(b->d_info);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_items2) (void)hipFree(b->d_items2);
+  if (b->d_nbrs) (void)hipFree(b->d_nbrs);
+  if (b->d_prog) (void)hipFree(b->d_prog);
+  if (b->d_err) (void)hipFree(b->d_err);
   delete b;
+}
+
+extern "C" lb_status lb_batch_status(lb_batch* b, void* stream) {
+  if (!b) return fail(LB_EINVAL, "batch is NULL");
+  if (!b->d_err) return LB_OK;
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t e = 0;
+  HIP_CHECK(hipStreamSynchronize(st));
+  HIP_CHECK(hipMemcpy(&e, b->d_err, sizeof(e), hipMemcpyDeviceToHost));
+  if (e) {
+    HIP_CHECK(hipMemset(b->d_err, 0, sizeof(uint32_t)));
+    return fail(LB_EHIP, "a persistent batched launch gave up waiting for a neighbouring strip (its blocks were not "
+                         "all resident, or the poll budget was too small); the result is incomplete");
+  }
+  return LB_OK;
 }
 
 // ------------------------------------------------------------------ autotuner

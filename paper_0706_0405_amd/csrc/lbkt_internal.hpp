@@ -42,3 +42,9 @@ struct LbktWorkItem {
 // columns), problems longest first, the two-step list dealt to the XCDs in runs.
 void lbkt_plan_batch(const lb_grid* grids, int nprob, int block_x, std::vector<LbktWorkItem>* items,
                      std::vector<LbktWorkItem>* items2);
+
+// Neighbours of each two-step item (the items whose columns its wavefronts read:
+// the strips left and right of it in its problem, wrapped for a periodic x axis;
+// -1 for none or itself).
+void lbkt_batch_neighbours(const lb_grid* grids, const std::vector<LbktWorkItem>& items2, int block_x,
+                           std::vector<int>* left, std::vector<int>* right);

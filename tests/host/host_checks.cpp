@@ -236,6 +236,29 @@ static void check_batch_plan(Rng& r, int nbatches) {
         for (int c : cnt) once = once && c == 1;
         CHECK(once, "problem %d: two-step strips not covered exactly once", p);
       }
+      // neighbours of the two-step items: the adjacent strips of the same problem
+      // (wrapped for a periodic x axis), symmetric, -1 at a non-periodic end
+      for (auto& g : grids) g.edge[1].kind = g.edge[0].kind = (r.pick(2) ? LB_BC_PERIODIC : LB_BC_OUTFLOW);
+      std::vector<int> left, right;
+      lbkt_batch_neighbours(grids.data(), b, bx, &left, &right);
+      CHECK(left.size() == b.size() && right.size() == b.size(), "neighbour list sizes");
+      for (size_t i = 0; i < b.size() && left.size() == b.size(); ++i) {
+        const auto& w = b[i];
+        const int ns = ((grids[w.prob].nx + 59) / 60 + bx / 64 - 1) / (bx / 64);
+        const bool per = grids[w.prob].edge[0].kind == LB_BC_PERIODIC;
+        const int want_l = w.strip > 0 ? w.strip - 1 : (per && ns > 1 ? ns - 1 : -1);
+        const int want_r = w.strip + 1 < ns ? w.strip + 1 : (per && ns > 1 ? 0 : -1);
+        for (int side = 0; side < 2; ++side) {
+          const int j = side ? right[i] : left[i];
+          const int want = side ? want_r : want_l;
+          if (want < 0 || want == w.strip) {
+            CHECK(j == -1, "item %zu: unexpected neighbour", i);
+          } else {
+            CHECK(j >= 0 && j < (int)b.size() && b[j].prob == w.prob && b[j].strip == want, "item %zu neighbour", i);
+            if (j >= 0 && j < (int)b.size()) CHECK((side ? left[j] : right[j]) == (int)i, "item %zu: not symmetric", i);
+          }
+        }
+      }
       for (size_t i = 1; i < a.size(); ++i) {   // one-step list: longest problems first
         const int64_t s0 = (int64_t)grids[a[i - 1].prob].nx * grids[a[i - 1].prob].ny;
         const int64_t s1 = (int64_t)grids[a[i].prob].nx * grids[a[i].prob].ny;

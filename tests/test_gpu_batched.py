@@ -309,3 +309,97 @@ def test_mixed_batch_takes_the_general_march(prec):
     for k, g in enumerate(grids):
         assert torch.equal(_bits(ref[k][:, :, :g.nx]), _bits(B.view(out, k)[:, :, :g.nx])), k
     B.close()
+
+
+def _run_batch(cfgs, prec, nsteps, tile=None, reps=1):
+    """The batch after nsteps steps (reps graph launches of nsteps/reps steps each) from
+    the workload's initial fields, with the given set_tile arguments."""
+    lb, grids, B, fa, fb, s = _make(cfgs, prec)
+    if tile is not None:
+        B.set_tile(*tile)
+    with torch.cuda.stream(s):
+        for _ in range(reps):
+            out = B.step(fa, fb, nsteps // reps)
+    torch.cuda.synchronize()
+    return lb, grids, B, out
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("block_x", [64, 256])
+def test_persistent_launch_bitwise_equals_per_pass_launches(prec, block_x):
+    """All two-step passes in one launch of co-resident blocks (progress counters between
+    neighbouring strips) give bitwise the per-pass launches' result: 4-row batches with
+    every x-edge kind (periodic ones wrap their neighbour waits), odd and even step counts
+    (single steps first), a mixed batch through the general march, graph replays that
+    continue the run, and capped block counts (many items per block)."""
+    from tests.test_gpu_parity import BC_SETS, _edge, _smooth_cfg
+    per = _edge("periodic")
+    xedges = [(_edge("outflow"), _edge("outflow")), (_edge("wall", split=2), _edge("inflow")),
+              (per, per), (_edge("inflow"), _edge("wall")), (per, per)]
+    widths = [61, 250, 130, 377, 1000, 8, 121, 1, 700, 64]
+    ny4 = [_smooth_cfg(nx, 4, [*xedges[k % len(xedges)], per, per], seed=k) for k, nx in enumerate(widths)]
+    mixed = ny4[:4] + [_smooth_cfg(77, 13, BC_SETS["walls"], seed=2), _smooth_cfg(300, 7, BC_SETS["xperiodic"], seed=4)]
+    for name, cfgs in (("ny4", ny4), ("mixed", mixed)):
+        for nsteps, reps, cap in ((40, 1, 0), (43, 1, 0), (40, 2, 0), (42, 1, 3)):
+            say("case persistent", prec, block_x, name, nsteps, reps, cap)
+            lb, grids, B, ref = _run_batch(cfgs, prec, nsteps, (block_x, 0, 0), reps)
+            ref = ref.clone()
+            B.close()
+            lb, grids, B, got = _run_batch(cfgs, prec, nsteps, (block_x, 0, cap or 4096), reps)
+            B.status()
+            for k, g in enumerate(grids):
+                assert torch.equal(_bits(B.view(got, k)[:, :, :g.nx]), _bits(B.view(ref, k)[:, :, :g.nx])), (name, k)
+            B.close()
+
+
+def test_persistent_launch_on_the_batched_workload():
+    """The 256-problem batched workload, 2000 steps in FP32 storage (the benchmark's
+    configuration), in one persistent launch: bitwise the per-pass launches' result."""
+    cfgs, _ = P.batched(nprob=256, seed=0, steps=2000)
+    lb, grids, B, ref = _run_batch(cfgs, "f32", 2000)
+    ref = ref.clone()
+    B.close()
+    lb, grids, B, got = _run_batch(cfgs, "f32", 2000, (256, 0, 4096))
+    B.status()
+    for k, g in enumerate(grids):
+        assert torch.equal(_bits(B.view(got, k)[:, :, :g.nx]), _bits(B.view(ref, k)[:, :, :g.nx])), k
+    B.close()
+
+
+def test_persistent_launch_gives_up_cleanly_on_a_tiny_poll_budget():
+    """Failure handling forced from the host: with a budget of one poll per wait, blocks
+    that find a neighbour not yet done give up, flag the batch and end (so do the others
+    at their next wait); the launch always ends, and lb_batch_status reports LB_EHIP
+    unless no wait needed a second poll, in which case the result must be exact. The
+    next call with the default budget runs normally."""
+    from paper_0706_0405_amd import _lib
+    cfgs, _ = P.batched(nprob=256, seed=0, steps=200)
+    lb, grids, B, ref = _run_batch(cfgs, "f32", 200)
+    ref = ref.clone()
+    B.close()
+    lb, grids, B, fa, fb, s = _make(cfgs, "f32")
+    B.set_tile(256, 0, 4096, 1)
+    with torch.cuda.stream(s):
+        out = B.step(fa, fb, 200)
+    torch.cuda.synchronize()
+    try:
+        B.status()
+        gave_up = False
+    except _lib.LbError as e:
+        gave_up = True
+        assert e.status == -5 and "gave up" in str(e), e
+    say("tiny poll budget: gave up", gave_up)
+    if not gave_up:
+        for k, g in enumerate(grids):
+            assert torch.equal(_bits(B.view(out, k)[:, :, :g.nx]), _bits(B.view(ref, k)[:, :, :g.nx])), k
+    B.status()                                       # the flag was cleared
+    for k, (c, g) in enumerate(zip(cfgs, grids)):    # a normal persistent call afterwards
+        lb.init(g, *_fields(c), prec="f32", out=B.view(fa, k))
+    B.set_tile(256, 0, 4096, 0)
+    with torch.cuda.stream(s):
+        out = B.step(fa, fb, 200)
+    torch.cuda.synchronize()
+    B.status()
+    for k, g in enumerate(grids):
+        assert torch.equal(_bits(B.view(out, k)[:, :, :g.nx]), _bits(B.view(ref, k)[:, :, :g.nx])), k
+    B.close()

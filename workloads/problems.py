@@ -322,7 +322,9 @@ def batched(nprob=256, seed=0, steps=2000, alpha=0.025, ny=4, screen=True, max_a
     stored FP64 screen rejected (the scheme leaves the physical range within `steps`
     steps: non-finite, rho <= 0 or rho > 1e6) is redrawn from the same generator.
     dx = 1/L, dt = alpha dx / c2, ny rows (periodic y, zero-gradient x).
-    Returns (cfgs, info) with info = {"vacuum_redraws", "unstable_redraws", "screened"}.
+    Returns (cfgs, info) with info = {"vacuum_redraws", "unstable_redraws", "screened", "attempts",
+    "accepted_fraction"}: the workload is the seeded distribution conditioned on the oracle
+    keeping the run in the physical range (about 60% of the draws for seed 0).
     """
     rejected = load_screen(seed, steps, alpha) if screen else None
     out, vac, unstable = [], 0, 0
@@ -338,7 +340,8 @@ def batched(nprob=256, seed=0, steps=2000, alpha=0.025, ny=4, screen=True, max_a
             break
         else:
             raise RuntimeError("slot %d: no accepted draw in %d attempts" % (p, max_attempts))
-    return out, {"vacuum_redraws": vac, "unstable_redraws": unstable, "screened": rejected is not None}
+    return out, {"vacuum_redraws": vac, "unstable_redraws": unstable, "screened": rejected is not None,
+                 "attempts": nprob + unstable, "accepted_fraction": nprob / (nprob + unstable)}
 
 
 # ------------------------------------------------------------------ von Neumann chooser inputs (batched draws)
