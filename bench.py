@@ -28,6 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# --profile-run: every leg with minimal repetition (one timed replay, no settle, no
+# one-at-a-time comparison), for rocprofv3 counter passes, which serialise dispatches
+PROFILE = False
 BYTES_PER_SITE = {"f64": 144, "f32": 72}   # 9 loads + 9 stores of the storage type per pass
 
 
@@ -125,12 +128,15 @@ def time_step(prec, steps, warmup, dev, per_pass=2, long_ms=20.0):
             lb.run(g, fa, fb, warmup, prec=prec, steps_per_pass=per_pass)
         run_k = lambda: lb.run(g, fa, fb, steps, prec=prec, use_graph=True, steps_per_pass=per_pass)  # noqa: E731
         run_k()   # capture (untimed)
-        times = replays(s, run_k)
+        times = replays(s, run_k, **({"settle_ms": 0.0, "reps": 1} if PROFILE else {}))
         ms = median(times)
         k_long = steps * max(1, math.ceil(long_ms / ms))   # a multiple of 4: the result stays in fa
-        run_long = lambda: lb.run(g, fa, fb, k_long, prec=prec, use_graph=True, steps_per_pass=per_pass)  # noqa: E731
-        run_long()
-        long_times = replays(s, run_long, settle_ms=0.0, reps=5)
+        if PROFILE:
+            k_long, long_times = steps, times
+        else:
+            run_long = lambda: lb.run(g, fa, fb, k_long, prec=prec, use_graph=True, steps_per_pass=per_pass)  # noqa: E731
+            run_long()
+            long_times = replays(s, run_long, settle_ms=0.0, reps=5)
         _, _, _, _, flags = lb.moments(g, fa, prec=prec)
         torch.cuda.synchronize()
     sites = g.nx * g.ny
@@ -191,6 +197,8 @@ def bench_batched(dev, steps=2000, nprob=256):
     import paper_0706_0405_amd as lb
     from workloads import problems as P
 
+    if PROFILE:
+        steps = 4
     cfgs, info = P.batched(nprob=nprob, seed=0, steps=steps)
     grids = [lb.Grid.from_workload(c) for c in cfgs]
     s = torch.cuda.Stream(device=dev)
@@ -207,13 +215,21 @@ def bench_batched(dev, steps=2000, nprob=256):
 
         from paper_0706_0405_amd import tuning
         init_all()
-        block_x = tuning.batch_block_for(B, fa, fb)   # block width chosen by timing (cached per device)
+        if PROFILE:   # one replay at every block width (the tuner's candidates), the last one 256
+            for bx in (64, 128, 256):
+                B.set_tile(bx)
+                init_all()
+                B.step(fa, fb, steps)
+            block_x = 256
+        else:
+            block_x = tuning.batch_block_for(B, fa, fb)   # block width chosen by timing (cached per device)
         init_all()
         B.step(fa, fb, steps)           # capture + first replay (untimed)
-        B.step(fa, fb, steps)           # settle (untimed)
+        if not PROFILE:
+            B.step(fa, fb, steps)       # settle (untimed)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         times = []
-        for _ in range(5):              # five timed replays, each from the initial fields
+        for _ in range(1 if PROFILE else 5):   # timed replays, each from the initial fields
             init_all()
             torch.cuda.synchronize()
             e0.record(s)
@@ -228,7 +244,7 @@ def bench_batched(dev, steps=2000, nprob=256):
             nonfinite += int(int(fl[1]) > 0)
         # the same problems one at a time (lb_run, one launch per two-step pass)
         t_single = 0.0
-        for k, (c, g) in enumerate(zip(cfgs, grids)):
+        for k, (c, g) in enumerate(zip(cfgs, grids) if not PROFILE else ()):
             rho, ux, uy, p = fields_to(dev, P.init_fields(c))
             f1 = lb.init(g, rho, ux, uy, p, prec="f32")
             f2 = lb.empty(g, "f32", dev)
@@ -248,7 +264,7 @@ def bench_batched(dev, steps=2000, nprob=256):
     mlups = sites * steps / (t_batch * 1e-3) / 1e6
     return {"problems": nprob, "steps": steps, "sites": sites, "draws": info, "block_x": block_x,
             "batched_ms": t_batch, "batched_ms_replays": spread(times),
-            "single_sum_ms": t_single, "speedup": t_single / t_batch,
+            "single_sum_ms": t_single, "speedup": t_single / t_batch if t_single else None,
             "batched_mlups": mlups, "steps_per_pass": 2,
             "mlups_vs_one_step_hbm_bound": mlups * 1e6 * BYTES_PER_SITE["f32"] / (HBM_PEAK_GBS * 1e9),
             "nonfinite_problems": nonfinite}
@@ -272,8 +288,11 @@ def bench_adjoint_step(dev, fwd_ms, nsteps=20):
         ga = lb.empty(g, "f64", dev)
         ga.normal_()
         gb = lb.empty(g, "f64", dev)
+        if PROFILE:
+            nsteps = 2
         states = [f] * nsteps   # nsteps adjoint steps, direct launches (no graph)
-        times = replays(s, lambda: api.adjoint_run(g, states, ga, gb, prec="f32"))
+        times = replays(s, lambda: api.adjoint_run(g, states, ga, gb, prec="f32"),
+                        **({"settle_ms": 0.0, "reps": 1} if PROFILE else {}))
         out = ga if nsteps % 2 == 0 else gb
         ms = median(times) / nsteps
         finite = bool(torch.isfinite(out[:, :, :g.nx]).all())
@@ -514,10 +533,14 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--prec", choices=["f64", "f32", "both"], default="both")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="minimal repetition in every leg (for rocprofv3 counter passes); figures not for reporting")
     ap.add_argument("--legs", default="all",
                     help="comma-separated subset of step,batched,adjoint,adjoint_step,vn,configs (for profiling "
                          "one leg; without 'step' the line carries no headline value)")
     args = ap.parse_args()
+    global PROFILE
+    PROFILE = args.profile_run
     legs = {"step", "batched", "adjoint", "adjoint_step", "vn", "configs"} if args.legs == "all" \
         else set(args.legs.split(","))
     if args.gpus != 1:
