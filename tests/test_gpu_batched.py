@@ -403,3 +403,38 @@ def test_persistent_launch_gives_up_cleanly_on_a_tiny_poll_budget():
     for k, g in enumerate(grids):
         assert torch.equal(_bits(B.view(out, k)[:, :, :g.nx]), _bits(B.view(ref, k)[:, :, :g.nx])), k
     B.close()
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13, 14])
+def test_persistent_launch_bitwise_on_random_batches(seed):
+    """Random batches (problem count, widths from 1 to 600 columns, x-edge kinds, for odd
+    seeds some problems that are not 4-row y-periodic, step count, block width and block cap drawn
+    from the seed): the persistent launch is bitwise the per-pass launches' result."""
+    from tests.test_gpu_parity import BC_SETS, _edge, _smooth_cfg
+    rng = np.random.default_rng(seed)
+    per = _edge("periodic")
+    kinds = [lambda: _edge("outflow"), lambda: _edge("inflow"), lambda: _edge("wall"),
+             lambda: _edge("wall", split=int(rng.integers(1, 4)))]
+    cfgs = []
+    for k in range(int(rng.integers(3, 24))):
+        nx = int(rng.integers(1, 601))
+        if rng.random() < (0.2 if seed % 2 else 0.0):   # even seeds: all 4-row y-periodic
+            cfgs.append(_smooth_cfg(max(nx, 8), int(rng.integers(2, 9)), BC_SETS["walls"], seed=100 * seed + k))
+        elif rng.random() < 0.25:
+            cfgs.append(_smooth_cfg(nx, 4, [per, per, per, per], seed=100 * seed + k))
+        else:
+            lo, hi = kinds[int(rng.integers(0, 4))](), kinds[int(rng.integers(0, 4))]()
+            cfgs.append(_smooth_cfg(nx, 4, [lo, hi, per, per], seed=100 * seed + k))
+    prec = ("f32", "f64")[int(rng.integers(0, 2))]
+    block_x = (64, 128, 256)[int(rng.integers(0, 3))]
+    nsteps = int(rng.integers(1, 60))
+    cap = (1, 2, 5, 4096)[int(rng.integers(0, 4))]
+    say("case persistent random", seed, prec, block_x, len(cfgs), [c["nx"] for c in cfgs], nsteps, cap)
+    lb, grids, B, ref = _run_batch(cfgs, prec, nsteps, (block_x, 0, 0))
+    ref = ref.clone()
+    B.close()
+    lb, grids, B, got = _run_batch(cfgs, prec, nsteps, (block_x, 0, cap))
+    B.status()
+    for k, g in enumerate(grids):
+        assert torch.equal(_bits(B.view(got, k)[:, :, :g.nx]), _bits(B.view(ref, k)[:, :, :g.nx])), k
+    B.close()
