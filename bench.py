@@ -192,7 +192,8 @@ def copy_bandwidth(dev, nbytes=9 * 2048 * 8192 * 8, reps=20):
 def bench_batched(dev, steps=2000, nprob=256):
     """cfg: 256 Riemann problems of uneven length, FP32 storage, one graph launch of
     `steps` steps (two steps per pass over the packed array) vs the sum of
-    single-problem lb_run runs (also two steps per pass)."""
+    single-problem lb_run runs (also two steps per pass); and the same batch in
+    FP64 storage at its default eight steps per pass against two."""
     import torch
     import paper_0706_0405_amd as lb
     from workloads import problems as P
@@ -260,6 +261,28 @@ def bench_batched(dev, steps=2000, nprob=256):
                 if not torch.equal(a, b):
                     raise RuntimeError("batched result differs from the single-problem run (problem %d)" % k)
         B.close()
+        # the same batch in double storage: the default 8 steps per pass (a strip's
+        # whole state in registers) against 2, bitwise the same result
+        f64 = None
+        if not PROFILE:
+            B = lb.Batch(grids, "f64")
+            fa, fb = B.empty(dev), B.empty(dev)
+            fa.zero_()
+            fb.zero_()
+            for k, (c, g) in enumerate(zip(cfgs, grids)):
+                lb.init(g, *fields_to(dev, P.init_fields(c)), prec="f64", out=B.view(fa, k))
+            f0 = fa.clone()
+            f64 = {}
+            outs = []
+            for name, spp in (("default", 0), ("two_steps_per_pass", 2)):
+                B.set_tile(64, spp)
+                fa.copy_(f0)
+                outs.append(B.step(fa, fb, steps).clone())
+                f64[name + "_ms"] = median(replays(s, lambda: B.step(fa, fb, steps), reps=3))
+            f64["steps_per_pass"] = 8
+            f64["bitwise_equal"] = bool(torch.equal(outs[0].view(torch.int64), outs[1].view(torch.int64)))
+            B.close()
+            del fa, fb, f0, outs
     sites = sum(g.nx * g.ny for g in grids)
     mlups = sites * steps / (t_batch * 1e-3) / 1e6
     return {"problems": nprob, "steps": steps, "sites": sites, "draws": info, "block_x": block_x,
@@ -267,7 +290,7 @@ def bench_batched(dev, steps=2000, nprob=256):
             "single_sum_ms": t_single, "speedup": t_single / t_batch if t_single else None,
             "batched_mlups": mlups, "steps_per_pass": 2,
             "mlups_vs_one_step_hbm_bound": mlups * 1e6 * BYTES_PER_SITE["f32"] / (HBM_PEAK_GBS * 1e9),
-            "nonfinite_problems": nonfinite}
+            "nonfinite_problems": nonfinite, "f64_storage": f64}
 
 
 def bench_adjoint_step(dev, fwd_ms, nsteps=20):

@@ -259,10 +259,14 @@ lb_status lb_batch_layout(const lb_batch* b, int64_t* offsets, int64_t* pitches,
 
 /* Set the launch shape of the batched step: block_x threads per work item (a
  * work item covers all rows of a strip of its problem); steps: time steps per
- * pass, 0 = the default, 1 or 2. blocks = 0: one launch per two-step pass (the
- * default). blocks > 0: all two-step passes of a call in ONE launch of at most
- * `blocks` co-resident blocks (fewer if fewer fit on the device at once), each
- * block taking its share of the work items pass after pass and waiting, before
+ * pass, 0 = the default, 1, 2, or 4, 6, 8 for a batch whose problems all have 4
+ * rows and a periodic y axis (the whole state of a strip then stays in registers
+ * for all the steps of a pass, and a wavefront produces 64 - 2 * steps columns);
+ * the default is 8 for such a batch in FP64 storage, else 2 (1 when a problem
+ * has ny < 2). blocks = 0: one launch per pass (the default). blocks > 0: all
+ * two-step passes of a call in ONE launch of at most `blocks` co-resident
+ * blocks (fewer if fewer fit on the device at once), each block taking its
+ * share of the work items pass after pass and waiting, before
  * each pass of an item, until the items whose columns it reads have finished the
  * previous pass (progress counters with release/acquire atomics); results are
  * bitwise those of the per-pass launches. rows (persistent launch only): polls
@@ -270,13 +274,18 @@ lb_status lb_batch_layout(const lb_batch* b, int64_t* offsets, int64_t* pitches,
  * flags the batch and ends, and so do the others at their next wait, so the launch
  * always terminates, with an incomplete result that lb_batch_status reports. Other
  * work on the device that keeps blocks of the launch from being resident can make
- * it give up. LB_EINVAL for a bad width, steps, or negative blocks or rows. */
+ * it give up. LB_EINVAL for a bad width, steps, or negative blocks or rows, for
+ * more than 2 steps on a batch that is not all 4-row y-periodic problems, or for
+ * more than 2 steps with blocks > 0 (the persistent launch runs two steps per
+ * pass; steps = 0 with blocks > 0 selects that). */
 lb_status lb_batch_set_tile(lb_batch* b, const lb_tile* tile);
 
 /* nsteps steps of every problem, all problems per launch, the launches captured
- * once in a HIP graph and replayed as one graph launch. Two time steps per pass
- * over the packed array (as lb_run) unless a problem has ny < 2 or
- * lb_batch_set_tile asked for steps = 1; results are bitwise the same either way.
+ * once in a HIP graph and replayed as one graph launch. Several time steps per
+ * pass over the packed array (as lb_batch_set_tile's steps sets: an even number of
+ * passes of that many steps, then two-step passes and single steps for the rest)
+ * unless a problem has ny < 2 or lb_batch_set_tile asked for steps = 1; results
+ * are bitwise the same either way.
  * Result in f_a when nsteps is even, else f_b. step index starts at 0 on the
  * first call and continues across calls. */
 lb_status lb_step_batched(lb_batch* b, void* f_a, void* f_b, int32_t nsteps, void* stream);

@@ -736,15 +736,17 @@ __device__ __forceinline__ int wrap_col(int c, int nx, bool perx) {
   return perx ? ((c % nx) + nx) % nx : min(max(c, 0), nx - 1);
 }
 
+// d: steps per pass (lane j holds column X0 - d + j; lanes d .. 63-d produce the
+// last step, the march of two steps per pass has d = 2).
 template <typename S>
-__device__ __forceinline__ Lane2 make_lane2(const KTConsts& K, int X0, int lane) {
+__device__ __forceinline__ Lane2 make_lane2(const KTConsts& K, int X0, int lane, int d = 2) {
   Lane2 L;
   const int nx = K.nx;
   L.perx = (K.kind[0] == BC_PERIODIC);
-  L.x = X0 - 2 + lane;
+  L.x = X0 - d + lane;
   L.xs = wrap_col(L.x, nx, L.perx);
   L.vbx = (uint32_t)L.xs * sizeof(S);
-  L.out = (lane >= 2) && (lane <= 61) && (L.x < nx);
+  L.out = (lane >= d) && (lane <= 63 - d) && (L.x < nx);
   L.vbo = L.out ? (uint32_t)L.x * sizeof(S) : 0u;
   return L;
 }
@@ -1426,6 +1428,133 @@ __device__ __forceinline__ void march2_ny4(const KTConsts& K, const V& fi, const
   row_second<XEDGE>(K, fo, L, 3, q2, q3, q0);
 }
 
+// The x ghosts of a row for the lanes at a non-periodic x edge, as ghost_x forms
+// them (x edges are walls, inflow or outflow here, periodic ones are handled by
+// the lanes' wrapped columns), written as selects instead of branches: the lane
+// holding column 0 takes its x-1 neighbour xm from the edge, the lane holding
+// column nx-1 its x+1 neighbour xp.
+__device__ __forceinline__ void ghost_x_select(const KTConsts& K, const Lane2& L, int y, const double cur[9],
+                                               double xm[9], double xp[9]) {
+  const bool l = (L.x == 0), r = (L.x == K.nx - 1);
+  const bool lc = l && (K.kind[0] == BC_INFLOW || y < K.split[0]);
+  const bool lm = l && !lc && K.kind[0] == BC_WALL, lo = l && !lc && K.kind[0] == BC_OUTFLOW;
+  const bool rc = r && (K.kind[1] == BC_INFLOW || y < K.split[1]);
+  const bool rm = r && !rc && K.kind[1] == BC_WALL, ro = r && !rc && K.kind[1] == BC_OUTFLOW;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    xm[i] = lc ? K.ga[0][i] : lm ? cur[mirror_x(i)] : lo ? cur[i] : xm[i];
+    xp[i] = rc ? K.ga[1][i] : rm ? cur[mirror_x(i)] : ro ? cur[i] : xp[i];
+  }
+}
+
+// One step of row y of the strip's state (rows y-1, y, y+1 = pt, ct, nt, held in
+// the storage type T) at the lane's column; xedge: the strip holds a
+// non-periodic x edge. STORE: the last step of the pass, stored by the output
+// lanes; otherwise rounded to the storage type into outt.
+template <bool STORE, bool XEDGE, class V, typename T>
+__device__ __forceinline__ void ny4_state_step_row(const KTConsts& K, const V& f, const Lane2& L, int y,
+                                                   const T pt[9], const T ct[9], const T nt[9], T outt[9]) {
+  double xm[9], xp[9], p[9], c[9], n[9], out[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {   // exact conversions (plain casts: the compiler places them)
+    p[i] = (double)pt[i];
+    c[i] = (double)ct[i];
+    n[i] = (double)nt[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    xm[i] = shr1z(c[i]);   // lanes 0 and 63 get 0: their results are never used
+    xp[i] = shl1z(c[i]);
+  }
+  if constexpr (XEDGE) ghost_x_select(K, L, y, c, xm, xp);
+  site_update(K, c, xp, xm, n, p, out);
+  if constexpr (STORE) {
+    if (L.out) f.store9(y, L.vbo, out);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) outt[i] = (T)(Sto<V>)out[i];
+  }
+}
+
+template <bool XEDGE, class V, typename T>
+__device__ __forceinline__ void ny4_state_step(const KTConsts& K, const V& fi, const Lane2& L, const T a0[9],
+                                               const T a1[9], const T a2[9], const T a3[9], T b0[9], T b1[9],
+                                               T b2[9], T b3[9]) {
+  ny4_state_step_row<false, XEDGE>(K, fi, L, 0, a3, a0, a1, b0);
+  __builtin_amdgcn_sched_barrier(0);
+  ny4_state_step_row<false, XEDGE>(K, fi, L, 1, a0, a1, a2, b1);
+  __builtin_amdgcn_sched_barrier(0);
+  ny4_state_step_row<false, XEDGE>(K, fi, L, 2, a1, a2, a3, b2);
+  __builtin_amdgcn_sched_barrier(0);
+  ny4_state_step_row<false, XEDGE>(K, fi, L, 3, a2, a3, a0, b3);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// A problem's constants re-read through a pointer that the compiler cannot see
+// through (as kernarg_consts does for the kernel-argument copy): the loads stay
+// scalar and invariant, so each step re-issues them instead of keeping ~70 SGPRs
+// of constants alive across all steps of the pass, spilled to VGPR lanes.
+__device__ __forceinline__ const KTConsts& consts_opaque(const KTConsts* p) {
+  auto kp = (const __attribute__((address_space(4))) KTConsts*)p;
+  asm volatile("" : "+s"(kp));
+  return *(const KTConsts*)kp;
+}
+
+// D (even) steps per pass on a strip of a 4-row grid with a periodic y axis: the
+// whole state of the strip's 64 columns stays in registers between the steps, so
+// the pass reads and writes the array once for D steps. Lane j holds column
+// X0 - D + j; step s is right on lanes s .. 63-s (each step loses one lane on
+// each side to its x-neighbours), so lanes D .. 63-D store and wavefronts start
+// every 64 - 2D columns. Every intermediate state is rounded to the storage type
+// and its x ghosts are formed as in a single step, so the result is bitwise that
+// of D single steps.
+template <int D, bool XEDGE, class V>
+__device__ __forceinline__ void march_ny4_deep(const KTConsts* Kp, const V& fi, const V& fo, const Lane2& L) {
+  static_assert(D >= 4 && D % 2 == 0, "the deep 4-row march takes an even number of steps >= 4");
+  using S = Sto<V>;
+  S a0[9], a1[9], a2[9], a3[9], b0[9], b1[9], b2[9], b3[9];
+  fi.raw9(0, L.vbx, a0);
+  fi.raw9(1, L.vbx, a1);
+  fi.raw9(2, L.vbx, a2);
+  fi.raw9(3, L.vbx, a3);
+  // steps 1 .. D-1 in registers (a -> b -> a ...), then step D from b, stored
+  for (int k = 0; k < D / 2 - 1; ++k) {
+    ny4_state_step<XEDGE>(consts_opaque(Kp), fi, L, a0, a1, a2, a3, b0, b1, b2, b3);
+    ny4_state_step<XEDGE>(consts_opaque(Kp), fi, L, b0, b1, b2, b3, a0, a1, a2, a3);
+  }
+  ny4_state_step<XEDGE>(consts_opaque(Kp), fi, L, a0, a1, a2, a3, b0, b1, b2, b3);
+  const KTConsts& K = consts_opaque(Kp);
+  S t[9];
+  ny4_state_step_row<true, XEDGE>(K, fo, L, 0, b3, b0, b1, t);
+  __builtin_amdgcn_sched_barrier(0);
+  ny4_state_step_row<true, XEDGE>(K, fo, L, 1, b0, b1, b2, t);
+  __builtin_amdgcn_sched_barrier(0);
+  ny4_state_step_row<true, XEDGE>(K, fo, L, 2, b1, b2, b3, t);
+  __builtin_amdgcn_sched_barrier(0);
+  ny4_state_step_row<true, XEDGE>(K, fo, L, 3, b2, b3, b0, t);
+}
+
+// One D-step work item of a batch of 4-row y-periodic problems: the strip of
+// block_x / 64 wavefronts (64 - 2D output columns each) of problem w.prob.
+template <typename S, int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_stepD_batched_ny4(
+    const KTConsts* __restrict__ Ks, const ProbInfo* __restrict__ info, const WorkItem* __restrict__ items,
+    const S* fin, S* fout) {
+  const WorkItem w = items[blockIdx.x];
+  const KTConsts& K = Ks[w.prob];
+  const int64_t off = info[w.prob].offset;
+  const int lane = threadIdx.x & 63;
+  const int X0 = (w.strip * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6)) * (64 - 2 * D);
+  if (X0 >= K.nx) return;
+  constexpr int AUX = sizeof(S) == 8 ? 2 : 0;   // the stores of k_step2
+  const View<S, AUX, false> fi = make_view<S, AUX, false>(K, fin + off), fo = make_view<S, AUX, false>(K, fout + off);
+  const Lane2 L = make_lane2<S>(K, X0, lane, D);
+  if (!L.perx && (X0 == 0 || X0 + 64 - D >= K.nx))
+    march_ny4_deep<D, true>(Ks + w.prob, fi, fo, L);
+  else
+    march_ny4_deep<D, false>(Ks + w.prob, fi, fo, L);
+}
+
 // One two-step work item of a batch: the strip of block_x / 64 wavefronts (60
 // output columns each) of problem w.prob, all rows. NY4: every problem of the
 // batch has 4 rows and a periodic y axis (an instantiation of its own, so that the
@@ -2093,8 +2222,11 @@ struct lb_batch {
   int nitems = 0;
   WorkItem* d_items2 = nullptr;   // work list of the two-step kernel (60-column wavefronts)
   int nitems2 = 0;
-  int steps = 2;                  // time steps per pass: 2 when every problem has ny >= 2
+  int steps = 2;                  // time steps per pass: 1, 2, or 4, 6, 8 (deep passes, below)
   bool all_ny4 = false;           // every problem has 4 rows and a periodic y axis
+  WorkItem* d_itemsD = nullptr;   // work list of the deep passes (64 - 2 * steps columns per wavefront)
+  int nitemsD = 0;
+  int planned_bx = 0, planned_steps = 0;   // the launch shape the work lists were made for
   int64_t step = 0;
   // captured graph
   hipGraphExec_t exec = nullptr;
@@ -2117,21 +2249,25 @@ struct lb_batch {
   uint32_t* d_err = nullptr;      // failure word: set when a wait gave up, cleared by lb_batch_status
 };
 
-void lbkt_plan_batch(const lb_grid* grids, int nprob, int block_x, std::vector<LbktWorkItem>* items_out,
-                     std::vector<LbktWorkItem>* items2_out) {
-  std::vector<WorkItem> items;
-  // longest problems first so the tail of a launch is made of short items
+// Problems by decreasing site count, so that the tail of a launch is made of
+// short items.
+static std::vector<int> batch_order(const lb_grid* grids, int nprob) {
   std::vector<int> order(nprob);
   for (int p = 0; p < nprob; ++p) order[p] = p;
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
     return grids[a].nx * (int64_t)grids[a].ny > grids[c].nx * (int64_t)grids[c].ny;
   });
+  return order;
+}
+
+// The strips of `width` output columns per wavefront, block_x / 64 wavefronts per
+// item, of every problem in `order`, dealt to the XCDs (below).
+static std::vector<WorkItem> batch_strips(const lb_grid* grids, const std::vector<int>& order, int block_x,
+                                          int width) {
   std::vector<WorkItem> items2;
   const int wpb = block_x / 64;
   for (int p : order) {
-    const int ns = (grids[p].nx + block_x - 1) / block_x;
-    for (int s = 0; s < ns; ++s) items.push_back({p, s});
-    const int ns2 = ((grids[p].nx + 59) / 60 + wpb - 1) / wpb;
+    const int ns2 = (int)cdiv(cdiv(grids[p].nx, width), wpb);
     for (int s = 0; s < ns2; ++s) items2.push_back({p, s});
   }
   // The hardware deals block ids round-robin to the 8 XCDs. Within each span of
@@ -2151,8 +2287,26 @@ void lbkt_plan_batch(const lb_grid* grids, int nprob, int block_x, std::vector<L
     }
     items2.swap(dealt);
   }
+  return items2;
+}
+
+void lbkt_plan_batch(const lb_grid* grids, int nprob, int block_x, std::vector<LbktWorkItem>* items_out,
+                     std::vector<LbktWorkItem>* items2_out) {
+  const std::vector<int> order = batch_order(grids, nprob);
+  std::vector<WorkItem> items;
+  for (int p : order) {
+    const int ns = (grids[p].nx + block_x - 1) / block_x;
+    for (int s = 0; s < ns; ++s) items.push_back({p, s});
+  }
+  std::vector<WorkItem> items2 = batch_strips(grids, order, block_x, 60);
   items_out->swap(items);
   items2_out->swap(items2);
+}
+
+void lbkt_plan_batch_deep(const lb_grid* grids, int nprob, int block_x, int depth,
+                          std::vector<LbktWorkItem>* items_out) {
+  std::vector<WorkItem> items = batch_strips(grids, batch_order(grids, nprob), block_x, 64 - 2 * depth);
+  items_out->swap(items);
 }
 
 void lbkt_batch_neighbours(const lb_grid* grids, const std::vector<LbktWorkItem>& items2, int block_x,
@@ -2175,6 +2329,21 @@ void lbkt_batch_neighbours(const lb_grid* grids, const std::vector<LbktWorkItem>
 }
 
 static lb_status batch_items(lb_batch* b) {
+  if (b->planned_bx == b->block_x && b->planned_steps == b->steps) return LB_OK;
+  if (b->d_itemsD) HIP_CHECK(hipFree(b->d_itemsD));
+  b->d_itemsD = nullptr;
+  b->nitemsD = 0;
+  if (b->steps > 2) {
+    std::vector<WorkItem> itemsD;
+    lbkt_plan_batch_deep(b->grids.data(), b->nprob, b->block_x, b->steps, &itemsD);
+    HIP_CHECK(hipMalloc(&b->d_itemsD, itemsD.size() * sizeof(WorkItem)));
+    HIP_CHECK(hipMemcpy(b->d_itemsD, itemsD.data(), itemsD.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    b->nitemsD = (int)itemsD.size();
+  }
+  if (b->planned_bx == b->block_x) {
+    b->planned_steps = b->steps;
+    return LB_OK;
+  }
   std::vector<WorkItem> items, items2;
   lbkt_plan_batch(b->grids.data(), b->nprob, b->block_x, &items, &items2);
   std::vector<int> left, right;
@@ -2201,14 +2370,22 @@ static lb_status batch_items(lb_batch* b) {
   HIP_CHECK(hipMemcpy(b->d_items2, items2.data(), items2.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
   b->nitems = (int)items.size();
   b->nitems2 = (int)items2.size();
+  b->planned_bx = b->block_x;
+  b->planned_steps = b->steps;
   return LB_OK;
 }
 
-// Two steps per pass unless asked otherwise, or some problem has ny < 2.
+// Steps per pass of the per-pass launches by default: two, or one when some
+// problem has ny < 2; for a batch of 4-row y-periodic problems in double storage,
+// eight. On the 256 Riemann problems (2000 steps, 64-thread items) double storage
+// takes 63.0 ms at two steps per pass and 38.6 / 40.1 / 43.4 ms at 8 / 6 / 4, while
+// float storage, whose two-step pass moves half the bytes and is bound by the
+// FP64 arithmetic, takes 36.4 ms at two and 38.2-39.7 ms at 4-8 (the 2D columns
+// of overlap per wavefront add arithmetic).
 static int batch_default_steps(const lb_batch* b) {
   for (const lb_grid& g : b->grids)
     if (g.ny < 2) return 1;
-  return 2;
+  return (b->all_ny4 && b->prec == LB_F64) ? 8 : 2;
 }
 
 extern "C" lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, int32_t prec_code, lb_batch** out) {
@@ -2260,10 +2437,10 @@ extern "C" lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, int32_
     lb_batch_destroy(b);
     return fail(LB_EHIP, "batch metadata upload failed");
   }
-  b->steps = batch_default_steps(b);
   b->all_ny4 = true;
   for (int p = 0; p < b->nprob; ++p)
     b->all_ny4 = b->all_ny4 && b->grids[p].ny == 4 && b->grids[p].edge[2].kind == LB_BC_PERIODIC;
+  b->steps = batch_default_steps(b);
   if ((s = batch_items(b))) {
     lb_batch_destroy(b);
     return s;
@@ -2286,13 +2463,18 @@ extern "C" lb_status lb_batch_set_tile(lb_batch* b, const lb_tile* tile) {
   if (tile && tile->block_x) bx = tile->block_x;
   if (bx != 64 && bx != 128 && bx != 256) return fail(LB_EINVAL, "tile block_x must be 64, 128 or 256");
   const int sp = tile ? tile->steps : 0;
-  if (sp < 0 || sp > 2) return fail(LB_EINVAL, "tile steps must be 0, 1 or 2");
+  if (!(sp == 0 || sp == 1 || sp == 2 || sp == 4 || sp == 6 || sp == 8))
+    return fail(LB_EINVAL, "tile steps must be 0, 1, 2, 4, 6 or 8");
   if (tile && (tile->blocks < 0 || tile->rows < 0)) return fail(LB_EINVAL, "tile blocks and rows must be >= 0");
-  b->steps = (sp == 1 || batch_default_steps(b) == 1) ? 1 : 2;
-  b->persist = tile && tile->blocks > 0;
+  const bool persist = tile && tile->blocks > 0;
+  if (sp > 2 && !b->all_ny4)
+    return fail(LB_EINVAL, "more than two steps per pass needs a batch of 4-row problems with a periodic y axis");
+  if (sp > 2 && persist) return fail(LB_EINVAL, "the persistent launch runs two steps per pass");
+  const int def = batch_default_steps(b);
+  b->steps = (def == 1 || sp == 1) ? 1 : sp != 0 ? sp : persist ? 2 : def;
+  b->persist = persist;
   b->persist_cap = tile ? tile->blocks : 0;
   b->spin_limit = (tile && tile->rows > 0) ? (uint32_t)tile->rows : (1u << 20);
-  if (bx == b->block_x) return LB_OK;
   b->block_x = bx;
   return batch_items(b);
 }
@@ -2322,6 +2504,28 @@ static lb_status launch_batched2(lb_batch* b, const void* fin, void* fout, hipSt
   return LB_OK;
 }
 
+// One pass of b->steps (4, 6 or 8) steps of a batch of 4-row y-periodic problems.
+static lb_status launch_batchedD(lb_batch* b, const void* fin, void* fout, hipStream_t st) {
+  using KD = void (*)(const KTConsts*, const ProbInfo*, const WorkItem*, const double*, double*);
+  using KF = void (*)(const KTConsts*, const ProbInfo*, const WorkItem*, const float*, float*);
+  KD kd = nullptr;
+  KF kf = nullptr;
+  switch (b->steps) {
+    case 4: kd = k_stepD_batched_ny4<double, 4>; kf = k_stepD_batched_ny4<float, 4>; break;
+    case 6: kd = k_stepD_batched_ny4<double, 6>; kf = k_stepD_batched_ny4<float, 6>; break;
+    case 8: kd = k_stepD_batched_ny4<double, 8>; kf = k_stepD_batched_ny4<float, 8>; break;
+    default: return fail(LB_EINVAL, "no deep batched kernel for this step count");
+  }
+  if (b->prec == LB_F64)
+    hipLaunchKernelGGL(kd, dim3(b->nitemsD), dim3(b->block_x), 0, st, b->d_consts, b->d_info, b->d_itemsD,
+                       (const double*)fin, (double*)fout);
+  else
+    hipLaunchKernelGGL(kf, dim3(b->nitemsD), dim3(b->block_x), 0, st, b->d_consts, b->d_info, b->d_itemsD,
+                       (const float*)fin, (float*)fout);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
 // All `passes` two-step passes from fa (passes even: the result lands in fa) in one
 // launch of co-resident blocks, after clearing the progress counters.
 template <typename S>
@@ -2345,10 +2549,16 @@ static lb_status launch_batched2_persistent(lb_batch* b, void* fa, void* fb, int
 
 // nsteps steps of the batch from fa (result in fa when nsteps is even): as
 // launch_steps, an even number of two-step passes after 0..3 single steps; the
-// passes in one persistent launch when asked for.
+// passes in one persistent launch when asked for. With deep passes (D = 4, 6, 8
+// steps each) an even number of them follows, and the two-step passes and single
+// steps cover the rest (fewer than 2D steps). Every pass swaps the buffers, and
+// all three counts are even for even nsteps.
 static lb_status batched_steps(lb_batch* b, void* fa, void* fb, int nsteps, hipStream_t st) {
-  const int pairs = (b->steps == 2) ? (nsteps / 2) & ~1 : 0;
-  const int singles = nsteps - 2 * pairs;
+  const int D = b->steps;
+  const int deep = (D > 2) ? (nsteps / D) & ~1 : 0;
+  const int rest = nsteps - D * deep;
+  const int pairs = (D >= 2) ? (rest / 2) & ~1 : 0;
+  const int singles = rest - 2 * pairs;
   int k = 0;
   lb_status s;
   for (int j = 0; j < singles; ++j, ++k)
@@ -2361,6 +2571,8 @@ static lb_status batched_steps(lb_batch* b, void* fa, void* fb, int nsteps, hipS
   }
   for (int j = 0; j < pairs; ++j, ++k)
     if ((s = launch_batched2(b, (k % 2 == 0) ? fa : fb, (k % 2 == 0) ? fb : fa, st))) return s;
+  for (int j = 0; j < deep; ++j, ++k)
+    if ((s = launch_batchedD(b, (k % 2 == 0) ? fa : fb, (k % 2 == 0) ? fb : fa, st))) return s;
   return LB_OK;
 }
 
@@ -2426,6 +2638,7 @@ extern "C" void lb_batch_destroy(lb_batch* b) {
   if (b->d_info) (void)hipFree(b->d_info);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_items2) (void)hipFree(b->d_items2);
+  if (b->d_itemsD) (void)hipFree(b->d_itemsD);
   if (b->d_nbrs) (void)hipFree(b->d_nbrs);
   if (b->d_prog) (void)hipFree(b->d_prog);
   if (b->d_err) (void)hipFree(b->d_err);

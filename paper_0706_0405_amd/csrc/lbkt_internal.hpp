@@ -43,6 +43,11 @@ struct LbktWorkItem {
 void lbkt_plan_batch(const lb_grid* grids, int nprob, int block_x, std::vector<LbktWorkItem>* items,
                      std::vector<LbktWorkItem>* items2);
 
+// Work list of the deep passes (depth = 4, 6 or 8 steps per pass): strips of
+// 64 - 2 * depth output columns per wavefront, ordered and dealt as items2.
+void lbkt_plan_batch_deep(const lb_grid* grids, int nprob, int block_x, int depth,
+                          std::vector<LbktWorkItem>* items);
+
 // Neighbours of each two-step item (the items whose columns its wavefronts read:
 // the strips left and right of it in its problem, wrapped for a periodic x axis;
 // -1 for none or itself).

@@ -49,8 +49,10 @@ def tile_for(grid: api.Grid, f_a, f_b, prec="f64", reps=10, refresh=False):
     return tile
 
 
-def batch_block_for(batch: api.Batch, f_a, f_b, steps=20, refresh=False):
-    """Best block_x for a batch (f_a/f_b are overwritten); applies it to the batch."""
+def batch_block_for(batch: api.Batch, f_a, f_b, steps=200, refresh=False, reps=3):
+    """Best block_x for a batch (f_a/f_b are overwritten); applies it to the batch.
+    Each width is timed as the median of `reps` graph launches of `steps` steps
+    (the widths differ by a few percent, less than one short launch varies)."""
     sig = "%d:%d" % (len(batch.grids), sum(g.nx * g.ny for g in batch.grids))
     d = _load()
     k = _key("batched", "f64" if batch.prec == 0 else "f32", sig)
@@ -62,12 +64,15 @@ def batch_block_for(batch: api.Batch, f_a, f_b, steps=20, refresh=False):
     for bx in (64, 128, 256):
         batch.set_tile(bx)
         batch.step(f_a, f_b, steps)            # capture
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        batch.step(f_a, f_b, steps)
-        e1.record(s)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            batch.step(f_a, f_b, steps)
+            e1.record(s)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = sorted(times)[len(times) // 2]
         if best_ms is None or ms < best_ms:
             best, best_ms = bx, ms
     batch.set_tile(best)

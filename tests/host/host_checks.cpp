@@ -259,6 +259,26 @@ static void check_batch_plan(Rng& r, int nbatches) {
           }
         }
       }
+      for (int depth : {4, 6, 8}) {   // deep passes: strips of 64 - 2 depth columns, each once
+        std::vector<LbktWorkItem> d;
+        lbkt_plan_batch_deep(grids.data(), n, bx, depth, &d);
+        const int w = 64 - 2 * depth, wpb = bx / 64;
+        std::vector<std::vector<int>> hit(n);
+        for (const auto& it : d) {
+          CHECK(it.prob >= 0 && it.prob < n && it.strip >= 0 && (int64_t)it.strip * wpb * w < grids[it.prob].nx,
+                "deep item (depth %d)", depth);
+          if (it.prob >= 0 && it.prob < n) hit[it.prob].push_back(it.strip);
+        }
+        for (int p = 0; p < n; ++p) {
+          const int ns = ((grids[p].nx + w - 1) / w + wpb - 1) / wpb;
+          std::vector<int> cnt(ns, 0);
+          for (int s : hit[p])
+            if (s >= 0 && s < ns) ++cnt[s];
+          bool once = (int)hit[p].size() == ns;
+          for (int c : cnt) once = once && c == 1;
+          CHECK(once, "problem %d: depth-%d strips not covered exactly once", p, depth);
+        }
+      }
       for (size_t i = 1; i < a.size(); ++i) {   // one-step list: longest problems first
         const int64_t s0 = (int64_t)grids[a[i - 1].prob].nx * grids[a[i - 1].prob].ny;
         const int64_t s1 = (int64_t)grids[a[i].prob].nx * grids[a[i].prob].ny;

@@ -56,10 +56,11 @@ def test_layout_is_aligned_and_packed():
     assert B.total == prev_end
 
 
-@pytest.mark.parametrize("spp", [1, 2])
+@pytest.mark.parametrize("spp", [1, 2, 4, 6, 8])
 @pytest.mark.parametrize("block_x", [64, 128, 256])
 def test_batched_equals_single_runs_bitwise(block_x, spp):
-    """One or two steps per pass over the packed array; the reference is each problem
+    """One, two, or 4-8 steps per pass over the packed array (the 4-row problems keep
+    a strip's whole state in registers through a pass); the reference is each problem
     run alone, one step per launch."""
     cfgs, _ = P.batched(nprob=48, seed=2, steps=200)
     lb, grids, B, fa, fb, s = _make(cfgs)
@@ -437,4 +438,54 @@ def test_persistent_launch_bitwise_on_random_batches(seed):
     B.status()
     for k, g in enumerate(grids):
         assert torch.equal(_bits(B.view(got, k)[:, :, :g.nx]), _bits(B.view(ref, k)[:, :, :g.nx])), k
+    B.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("depth", [4, 6, 8])
+def test_deep_passes_bitwise_on_every_x_edge_and_ragged_width(prec, depth):
+    """Passes of 4, 6 and 8 steps on 4-row y-periodic problems: every x-edge kind (walls
+    with split inflow segments, inflow, outflow, periodic), widths around the 64 - 2D
+    output columns of a wavefront and the block widths, step counts that leave two-step
+    passes and single steps before the deep ones; bitwise the single-step result."""
+    from tests.test_gpu_parity import _edge, _smooth_cfg
+    per = _edge("periodic")
+    xedges = [(_edge("outflow"), _edge("outflow")), (_edge("wall", split=2), _edge("inflow")),
+              (per, per), (_edge("inflow"), _edge("wall")), (_edge("wall"), _edge("outflow", split=1))]
+    w = 64 - 2 * depth
+    widths = [1, 2, w - 1, w, w + 1, 2 * w, 2 * w + 3, 4 * w - 1, 300, 1000, 7, 64]
+    cfgs = [_smooth_cfg(nx, 4, [*xedges[k % len(xedges)], per, per], seed=k) for k, nx in enumerate(widths)]
+    for block_x in (64, 256):
+        for nsteps in (depth, 2 * depth, 2 * depth + 3, 5 * depth + 2):
+            say("case deep", prec, depth, block_x, nsteps)
+            lb, grids, B, ref = _run_batch(cfgs, prec, nsteps, (block_x, 1, 0))
+            ref = ref.clone()
+            B.close()
+            lb, grids, B, got = _run_batch(cfgs, prec, nsteps, (block_x, depth, 0))
+            for k, g in enumerate(grids):
+                assert torch.equal(_bits(B.view(got, k)[:, :, :g.nx]), _bits(B.view(ref, k)[:, :, :g.nx])), (k, nsteps)
+            B.close()
+
+
+def test_deep_pass_requests_that_cannot_run_are_rejected():
+    """More than two steps per pass needs 4-row y-periodic problems and the per-pass
+    launch; other step counts are invalid."""
+    from paper_0706_0405_amd import _lib
+    from tests.test_gpu_parity import BC_SETS, _edge, _smooth_cfg
+    per = _edge("periodic")
+    ny4 = [_smooth_cfg(100, 4, [_edge("outflow"), _edge("outflow"), per, per], seed=1)]
+    mixed = ny4 + [_smooth_cfg(77, 13, BC_SETS["walls"], seed=2)]
+    lb, grids, B, fa, fb, s = _make(ny4)
+    for bad in ((64, 3, 0), (64, 10, 0), (64, 4, 8)):
+        with pytest.raises(_lib.LbError) as e:
+            B.set_tile(*bad)
+        assert e.value.status == -1, bad
+    B.set_tile(64, 8, 0)
+    B.set_tile(64, 0, 8)       # persistent: two steps per pass
+    B.close()
+    lb, grids, B, fa, fb, s = _make(mixed)
+    with pytest.raises(_lib.LbError) as e:
+        B.set_tile(64, 4, 0)
+    assert e.value.status == -1
+    B.set_tile(64, 2, 0)
     B.close()
