@@ -262,8 +262,8 @@ lb_status lb_batch_layout(const lb_batch* b, int64_t* offsets, int64_t* pitches,
  * pass, 0 = the default, 1, 2, or 4, 6, 8 for a batch whose problems all have 4
  * rows and a periodic y axis (the whole state of a strip then stays in registers
  * for all the steps of a pass, and a wavefront produces 64 - 2 * steps columns);
- * the default is 8 for such a batch in FP64 storage, else 2 (1 when a problem
- * has ny < 2). blocks = 0: one launch per pass (the default). blocks > 0: all
+ * the default for such a batch is 4 in FP32 and 8 in FP64 storage, else 2 (1
+ * when a problem has ny < 2). blocks = 0: one launch per pass (the default). blocks > 0: all
  * two-step passes of a call in ONE launch of at most `blocks` co-resident
  * blocks (fewer if fewer fit on the device at once), each block taking its
  * share of the work items pass after pass and waiting, before

@@ -1435,11 +1435,13 @@ __device__ __forceinline__ void march2_ny4(const KTConsts& K, const V& fi, const
 // column nx-1 its x+1 neighbour xp.
 __device__ __forceinline__ void ghost_x_select(const KTConsts& K, const Lane2& L, int y, const double cur[9],
                                                double xm[9], double xp[9]) {
+  // the edge's kind and split are read first and combined without short-circuit
+  // evaluation, so no per-lane branch guards the reads
+  const int k0 = K.kind[0], k1 = K.kind[1], s0 = K.split[0], s1 = K.split[1];
   const bool l = (L.x == 0), r = (L.x == K.nx - 1);
-  const bool lc = l && (K.kind[0] == BC_INFLOW || y < K.split[0]);
-  const bool lm = l && !lc && K.kind[0] == BC_WALL, lo = l && !lc && K.kind[0] == BC_OUTFLOW;
-  const bool rc = r && (K.kind[1] == BC_INFLOW || y < K.split[1]);
-  const bool rm = r && !rc && K.kind[1] == BC_WALL, ro = r && !rc && K.kind[1] == BC_OUTFLOW;
+  const bool c0 = (k0 == BC_INFLOW) | (y < s0), c1 = (k1 == BC_INFLOW) | (y < s1);
+  const bool lc = l & c0, lm = l & !c0 & (k0 == BC_WALL), lo = l & !c0 & (k0 == BC_OUTFLOW);
+  const bool rc = r & c1, rm = r & !c1 & (k1 == BC_WALL), ro = r & !c1 & (k1 == BC_OUTFLOW);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     xm[i] = lc ? K.ga[0][i] : lm ? cur[mirror_x(i)] : lo ? cur[i] : xm[i];
@@ -1544,7 +1546,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const KTConsts& K = Ks[w.prob];
   const int64_t off = info[w.prob].offset;
   const int lane = threadIdx.x & 63;
-  const int X0 = (w.strip * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6)) * (64 - 2 * D);
+  // the strip's first column, the same for the whole wavefront (so the tests on it
+  // below are wave-uniform branches)
+  const int X0 = __builtin_amdgcn_readfirstlane(
+      (w.strip * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6)) * (64 - 2 * D));
   if (X0 >= K.nx) return;
   constexpr int AUX = sizeof(S) == 8 ? 2 : 0;   // the stores of k_step2
   const View<S, AUX, false> fi = make_view<S, AUX, false>(K, fin + off), fo = make_view<S, AUX, false>(K, fout + off);
@@ -2376,16 +2381,15 @@ static lb_status batch_items(lb_batch* b) {
 }
 
 // Steps per pass of the per-pass launches by default: two, or one when some
-// problem has ny < 2; for a batch of 4-row y-periodic problems in double storage,
-// eight. On the 256 Riemann problems (2000 steps, 64-thread items) double storage
-// takes 63.0 ms at two steps per pass and 38.6 / 40.1 / 43.4 ms at 8 / 6 / 4, while
-// float storage, whose two-step pass moves half the bytes and is bound by the
-// FP64 arithmetic, takes 36.4 ms at two and 38.2-39.7 ms at 4-8 (the 2D columns
-// of overlap per wavefront add arithmetic).
+// problem has ny < 2; for a batch of 4-row y-periodic problems, 4 in float and 8
+// in double storage. On the 256 Riemann problems (2000 steps, 64-thread items)
+// float storage takes 36.3 ms at two steps per pass, 32.1 / 33.5 / 32.8 ms at
+// 4 / 6 / 8; double storage 62.5 ms at two, 33.3 / 31.5 / 30.7 ms at 4 / 6 / 8.
 static int batch_default_steps(const lb_batch* b) {
   for (const lb_grid& g : b->grids)
     if (g.ny < 2) return 1;
-  return (b->all_ny4 && b->prec == LB_F64) ? 8 : 2;
+  if (!b->all_ny4) return 2;
+  return b->prec == LB_F64 ? 8 : 4;
 }
 
 extern "C" lb_status lb_batch_create(int32_t nprob, const lb_grid* grids, int32_t prec_code, lb_batch** out) {

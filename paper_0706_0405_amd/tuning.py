@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import json
 import os
+import time
 
 import torch
 
@@ -49,33 +50,41 @@ def tile_for(grid: api.Grid, f_a, f_b, prec="f64", reps=10, refresh=False):
     return tile
 
 
-def batch_block_for(batch: api.Batch, f_a, f_b, steps=200, refresh=False, reps=3):
+def batch_block_for(batch: api.Batch, f_a, f_b, steps=200, refresh=False, reps=3, settle_ms=250.0):
     """Best block_x for a batch (f_a/f_b are overwritten); applies it to the batch.
-    Each width is timed as the median of `reps` graph launches of `steps` steps
-    (the widths differ by a few percent, less than one short launch varies)."""
+    The widths are timed in `reps` interleaved rounds (one graph launch of `steps`
+    steps each, after an untimed launch that captures it), after untimed launches
+    that keep the GPU busy for settle_ms (clocks ramp up after an idle period);
+    the median per width decides (the widths differ by a few percent)."""
     sig = "%d:%d" % (len(batch.grids), sum(g.nx * g.ny for g in batch.grids))
     d = _load()
     k = _key("batched", "f64" if batch.prec == 0 else "f32", sig)
     if k in d and not refresh:
         batch.set_tile(d[k]["block_x"])
         return d[k]["block_x"]
-    best, best_ms = None, None
+    widths = (64, 128, 256)
     s = torch.cuda.current_stream()
-    for bx in (64, 128, 256):
-        batch.set_tile(bx)
-        batch.step(f_a, f_b, steps)            # capture
-        times = []
-        for _ in range(reps):
+    batch.set_tile(widths[0])
+    t0 = time.perf_counter()
+    n = 0
+    while n < 2 or (time.perf_counter() - t0) * 1e3 < settle_ms:
+        batch.step(f_a, f_b, steps)
+        torch.cuda.synchronize()
+        n += 1
+    times = {bx: [] for bx in widths}
+    for _ in range(reps):
+        for bx in widths:
+            batch.set_tile(bx)
+            batch.step(f_a, f_b, steps)            # capture (untimed)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
             batch.step(f_a, f_b, steps)
             e1.record(s)
             torch.cuda.synchronize()
-            times.append(e0.elapsed_time(e1))
-        ms = sorted(times)[len(times) // 2]
-        if best_ms is None or ms < best_ms:
-            best, best_ms = bx, ms
+            times[bx].append(e0.elapsed_time(e1))
+    med = {bx: sorted(v)[len(v) // 2] for bx, v in times.items()}
+    best = min(widths, key=lambda bx: med[bx])
     batch.set_tile(best)
-    d[k] = {"block_x": best, "ms": best_ms, "steps": steps}
+    d[k] = {"block_x": best, "ms": med[best], "steps": steps, "ms_by_width": {str(b): m for b, m in med.items()}}
     _store(d)
     return best

@@ -249,7 +249,7 @@ def test_autotuners_pick_valid_shapes_and_keep_results(tmp_path, monkeypatch):
         a, b = B.empty(), B.empty()
         a.zero_()
         b.zero_()
-        bx = tuning.batch_block_for(B, a, b, steps=4)
+        bx = tuning.batch_block_for(B, a, b, steps=4, settle_ms=0.0)
         say("tuned batch block", bx)
         assert bx in (64, 128, 256)
     finally:
@@ -488,4 +488,36 @@ def test_deep_pass_requests_that_cannot_run_are_rejected():
         B.set_tile(64, 4, 0)
     assert e.value.status == -1
     B.set_tile(64, 2, 0)
+    B.close()
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23, 24, 25, 26])
+def test_deep_passes_bitwise_on_random_batches(seed):
+    """Random 4-row y-periodic batches (problem count, widths from 1 to 700 columns,
+    x-edge kinds with split segments, block width and step count drawn from the seed;
+    every storage type at every depth): bitwise the single-step result."""
+    from tests.test_gpu_parity import _edge, _smooth_cfg
+    rng = np.random.default_rng(seed)
+    per = _edge("periodic")
+    kinds = [lambda: _edge("outflow"), lambda: _edge("inflow"), lambda: _edge("wall"),
+             lambda: _edge("wall", split=int(rng.integers(1, 4))), lambda: _edge("outflow", split=int(rng.integers(1, 4)))]
+    cfgs = []
+    for k in range(int(rng.integers(2, 20))):
+        nx = int(rng.integers(1, 701))
+        if rng.random() < 0.25:
+            cfgs.append(_smooth_cfg(nx, 4, [per, per, per, per], seed=100 * seed + k))
+        else:
+            lo, hi = kinds[int(rng.integers(0, 5))](), kinds[int(rng.integers(0, 5))]()
+            cfgs.append(_smooth_cfg(nx, 4, [lo, hi, per, per], seed=100 * seed + k))
+    prec = ("f32", "f64")[seed % 2]
+    depth = (4, 6, 8)[seed % 3]   # the six seeds cover each storage type at each depth
+    block_x = (64, 128, 256)[int(rng.integers(0, 3))]
+    nsteps = int(rng.integers(depth, 8 * depth))
+    say("case deep random", seed, prec, depth, block_x, nsteps, [c["nx"] for c in cfgs])
+    lb, grids, B, ref = _run_batch(cfgs, prec, nsteps, (block_x, 1, 0))
+    ref = ref.clone()
+    B.close()
+    lb, grids, B, got = _run_batch(cfgs, prec, nsteps, (block_x, depth, 0))
+    for k, g in enumerate(grids):
+        assert torch.equal(_bits(B.view(got, k)[:, :, :g.nx]), _bits(B.view(ref, k)[:, :, :g.nx])), k
     B.close()
