@@ -47,7 +47,7 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel, prec):
-    """HBM bytes per launch of `kernel` ("k_step" or "k_step2") from a committed
+    """HBM bytes per launch of `kernel` ("k_step", "k_step2" or "k_step3") from a committed
     rocprofv3 counter summary, if it was taken from the current kernel source;
     else None."""
     path = os.path.join(ROOT, "profiles", "traffic_step_roofline_grid.txt")
@@ -108,7 +108,7 @@ def spread(v):
 
 def time_step(prec, steps, warmup, dev, per_pass=2, long_ms=20.0):
     """lb_run on the roofline grid with `per_pass` time steps per launch (steps a
-    multiple of 4, so that a two-step run is all two-step passes): W warm-up steps,
+    multiple of 12, so that a run is all passes of per_pass steps): W warm-up steps,
     the K-step graph captured, then the median of 7 replays of exactly K steps
     (after the settle replays); as a check, the median of 5 replays of a graph of
     K_long >= K steps lasting at least long_ms each."""
@@ -145,7 +145,7 @@ def time_step(prec, steps, warmup, dev, per_pass=2, long_ms=20.0):
     mlups = sites * steps / (ms * 1e-3) / 1e6
     long_mlups = sites * k_long / (median(long_times) * 1e-3) / 1e6
     achieved = BYTES_PER_SITE[prec] * sites / (per_launch_ms * 1e-3) / 1e9
-    kname = "k_step" if per_pass == 1 else "k_step2"
+    kname = {1: "k_step", 2: "k_step2", 3: "k_step3"}[per_pass]
     traffic = measured_traffic(kname, prec)
     # the one-step HBM bound on the update rate: peak / (bytes per site per step)
     bound_mlups = HBM_PEAK_GBS * 1e9 / BYTES_PER_SITE[prec] / 1e6
@@ -158,7 +158,7 @@ def time_step(prec, steps, warmup, dev, per_pass=2, long_ms=20.0):
                                    "ratio_to_value": long_mlups / mlups}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "%s<%s>" % (kname, "double" if prec == "f64" else "float"),
+                     "kernel": kname if per_pass == 3 else "%s<%s>" % (kname, "double" if prec == "f64" else "float"),
                      "launch_ms": per_launch_ms,
                      "algorithmic_bytes_per_launch": BYTES_PER_SITE[prec] * sites},
     }
@@ -200,7 +200,7 @@ def bench_batched(dev, steps=2000, nprob=256):
     from workloads import problems as P
 
     if PROFILE:
-        steps = 4
+        steps = 8   # two deep passes of four steps (the default depth in FP32 storage)
     cfgs, info = P.batched(nprob=nprob, seed=0, steps=steps)
     grids = [lb.Grid.from_workload(c) for c in cfgs]
     s = torch.cuda.Stream(device=dev)
@@ -581,7 +581,9 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    args.steps += (-args.steps) % 4   # all two-step passes (their count even), result in the first buffer
+    # a multiple of 12: all two-step passes (their count even) or all three-step
+    # passes (an even count), the result in the first buffer either way
+    args.steps += (-args.steps) % 12
 
     import torch
     import paper_0706_0405_amd as lb
@@ -591,11 +593,17 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda", 0)
 
-    res, one = {}, {}
+    res, one, two = {}, {}, {}
     for prec in (("f64", "f32") if args.prec == "both" else (args.prec,)) if "step" in legs else ():
-        log("timing", prec, "lb_run on the roofline grid, two steps per pass")
-        res[prec] = time_step(prec, args.steps, args.warmup, dev, per_pass=2)
+        # lb_run's default: three steps per pass on FP64 arrays, two on FP32
+        spp = 3 if prec == "f64" else 2
+        log("timing", prec, "lb_run on the roofline grid, %d steps per pass" % spp)
+        res[prec] = time_step(prec, args.steps, args.warmup, dev, per_pass=spp)
         log(prec, json.dumps(res[prec]))
+        if prec == "f64":
+            log("timing", prec, "lb_run on the roofline grid, two steps per pass")
+            two[prec] = time_step(prec, args.steps, args.warmup, dev, per_pass=2)
+            log(prec, json.dumps(two[prec]))
         log("timing", prec, "lb_run on the roofline grid, one step per launch")
         one[prec] = time_step(prec, args.steps, args.warmup, dev, per_pass=1)
         log(prec, json.dumps(one[prec]))
@@ -604,7 +612,7 @@ def main():
     if res:
         log("timing a device copy of the same size")
         copy = copy_bandwidth(dev)
-        for r_ in list(res.values()) + list(one.values()):
+        for r_ in list(res.values()) + list(one.values()) + list(two.values()):
             r_["roofline"]["frac_of_device_copy"] = r_["roofline"]["achieved"] / copy["gbs"]
     extras = {}
     if not args.no_extras:
@@ -642,8 +650,10 @@ def main():
         "value": r["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "double-Mach-reflection field, %dx%d grid, FP64 storage, FDLB steps through lb_run "
-                               "(two time steps per pass)" % tuple(r["grid"]), "storage": head, "steps_per_pass": 2},
+        "config": {"workload": "double-Mach-reflection field, %dx%d grid, %s storage, FDLB steps through lb_run "
+                               "(%d time steps per pass)" % (r["grid"][0], r["grid"][1], head.upper(),
+                                                             r["steps_per_pass"]),
+                   "storage": head, "steps_per_pass": r["steps_per_pass"]},
         "roofline": r["roofline"],
         "replays": r["replays"],
         "mlups_vs_one_step_hbm_bound": r["mlups_vs_one_step_hbm_bound"],
@@ -652,6 +662,10 @@ def main():
         "cpu_baseline": cpu,
         "device_copy": copy,
     }
+    if "f64" in two:
+        line["fp64_two_steps_per_pass"] = {"value": two["f64"]["mlups"], "unit": "MLUPS",
+                                           "ms_per_step": two["f64"]["ms_per_step"], "steps_per_pass": 2,
+                                           "replays": two["f64"]["replays"], "roofline": two["f64"]["roofline"]}
     if "f32" in res and head != "f32":
         line["fp32_storage"] = {"value": res["f32"]["mlups"], "unit": "MLUPS", "ms_per_step": res["f32"]["ms_per_step"],
                                 "dtype": "f64 arithmetic, f32 storage", "steps_per_pass": 2,

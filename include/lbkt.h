@@ -120,15 +120,18 @@ typedef struct {
  * the XCDs in bands), each looping over tiles. All zero (or a NULL tile) = the
  * default: 256 x 32 tiles, one block per tile, shrunk on small grids (rows down
  * to 2, then columns) to give at least 1024 tiles; the two-step pass takes at
- * most 11 rows (double) or 24 rows (float) by default. In the two-step pass a
- * wavefront of 64 threads produces 60 columns, so a tile is block_x / 64 * 60
- * columns wide. */
+ * most 11 rows (double) or 24 rows (float) by default, the three-step pass 11
+ * rows. In the two-step pass a wavefront of 64 threads produces 60 columns, in
+ * the three-step pass 58, so a tile is block_x / 64 * 60 (58) columns wide. */
 typedef struct {
   int32_t block_x, rows, blocks;
-  int32_t steps;   /* lb_run only: time steps per pass over the array, 1 or 2; 0 = the
-                      default, 2 (one step per pass when ny < 2). Two steps per pass
-                      keep the intermediate state in registers (temporal blocking):
-                      half the HBM traffic per step, bitwise the result of single steps. */
+  int32_t steps;   /* lb_run only: time steps per pass over the array, 1, 2 or 3; 0 = the
+                      default: 3 for FP64 arrays below 4 GiB with ny >= 32, else 2 (1 when
+                      ny < 2). Several steps per pass keep the intermediate states in
+                      registers (temporal blocking): 1/2 or 1/3 of the HBM traffic per
+                      step, bitwise the result of single steps. An explicit 3 runs on
+                      FP64 arrays below 4 GiB with ny >= 3; elsewhere LB_EUNSUPPORTED
+                      from lb_run. */
 } lb_tile;
 
 /* Fill grid->lambda with Eq. (SEC-VON-13): c1 dx, c1 dx/10 (i = 1..4), 0 (i = 5..8). */
@@ -159,7 +162,9 @@ lb_status lb_step_tiled(const lb_grid* grid, int32_t prec, const void* f_in, voi
 
 /* nsteps ping-pong steps from f_a at time index step0. The result is in f_a when
  * nsteps is even, else in f_b; the other array is left holding an intermediate
- * state (with two steps per pass, not necessarily that of step nsteps-1).
+ * state (with several steps per pass, not necessarily that of step nsteps-1).
+ * With two steps per pass: 0-3 single steps, then an even number of two-step
+ * passes; with three: 0-2 single steps, then nsteps / 3 three-step passes.
  * use_graph != 0 captures the launches in a HIP graph (cached: a repeated call with
  * the same arguments replays it). Every launch shape and steps setting gives
  * bitwise the same result. */

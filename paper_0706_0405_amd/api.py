@@ -126,7 +126,7 @@ def init(grid: Grid, rho, ux, uy, p, prec="f64", out=None):
 
 def _tile(tile, steps=0):
     """(block_x, rows[, blocks[, steps]]) -> lb_tile; None = the library's default shape.
-    steps: time steps per pass of lb_run (0 = the tile's own, else the default; 1 or 2)."""
+    steps: time steps per pass of lb_run (0 = the tile's own, else the default; 1, 2 or 3)."""
     if tile is None and not steps:
         return None
     t = tuple(tile) if tile is not None else (0, 0)
@@ -148,7 +148,8 @@ def step(grid: Grid, f_in, f_out, n=0, prec="f64", tile=None):
 
 def run(grid: Grid, f_a, f_b, nsteps, n0=0, prec="f64", use_graph=False, tile=None, steps_per_pass=0):
     """nsteps ping-pong steps; returns the tensor holding the result (lb_run).
-    steps_per_pass: 1 = one step per launch, 2 = two (0 = the library default)."""
+    steps_per_pass: 1 = one step per launch, 2 = two, 3 = three (FP64 arrays); 0 = the
+    library default (three on FP64 arrays below 4 GiB with ny >= 32, else two)."""
     pr = _prec(prec)
     _check_f(grid, pr, f_a, "f_a")
     _check_f(grid, pr, f_b, "f_b")

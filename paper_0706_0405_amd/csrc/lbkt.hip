@@ -403,10 +403,19 @@ __device__ __forceinline__ ViewG<S> make_view_g(const KTConsts& K, const void* p
 template <class V>
 using Sto = typename V::Sto;
 
+// v held in scalar registers: a grid constant read this way is loaded by a
+// scalar load and then chosen per lane, instead of the compiler choosing its
+// address per lane and reading it with vector loads (a form that gave wrong edge
+// ghosts inside the three-step kernel).
+__device__ __forceinline__ double uni(double v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
 // Ghost row of y edge E (2: below row 0, 3: above row ny-1) at column x
 // (vbx = x * sizeof(S)). Edge indices are compile-time constants so no per-lane
 // indexing of K occurs.
-template <int E, class V>
+template <int E, class V, bool UNI = false>
 __device__ __forceinline__ void ghost_row(const KTConsts& K, const V& f, int x, uint32_t vbx, int ish,
                                           double r[9]) {
   const int kind = K.kind[E];
@@ -428,11 +437,16 @@ __device__ __forceinline__ void ghost_row(const KTConsts& K, const V& f, int x, 
   } else {
     const bool a = (kind == BC_INFLOW) || (x < ish);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) r[i] = a ? K.ga[E][i] : K.gb[E][i];
+    for (int i = 0; i < 9; ++i) {
+      if constexpr (UNI)
+        r[i] = a ? uni(K.ga[E][i]) : uni(K.gb[E][i]);
+      else
+        r[i] = a ? K.ga[E][i] : K.gb[E][i];
+    }
   }
   if (x < K.split[E]) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) r[i] = K.ga[E][i];
+    for (int i = 0; i < 9; ++i) r[i] = UNI ? uni(K.ga[E][i]) : K.ga[E][i];
   }
 }
 
@@ -751,9 +765,37 @@ __device__ __forceinline__ Lane2 make_lane2(const KTConsts& K, int X0, int lane,
   return L;
 }
 
+// The x ghosts of a row for the lanes at a non-periodic x edge, as ghost_x forms
+// them (x edges are walls, inflow or outflow here, periodic ones are handled by
+// the lanes' wrapped columns), written as selects instead of branches: the lane
+// holding column 0 takes its x-1 neighbour xm from the edge, the lane holding
+// column nx-1 its x+1 neighbour xp.
+template <bool UNI = false>
+__device__ __forceinline__ void ghost_x_select(const KTConsts& K, const Lane2& L, int y, const double cur[9],
+                                               double xm[9], double xp[9]) {
+  // the edge's kind and split are read first and combined without short-circuit
+  // evaluation, so no per-lane branch guards the reads
+  const int k0 = K.kind[0], k1 = K.kind[1], s0 = K.split[0], s1 = K.split[1];
+  const bool l = (L.x == 0), r = (L.x == K.nx - 1);
+  const bool c0 = (k0 == BC_INFLOW) | (y < s0), c1 = (k1 == BC_INFLOW) | (y < s1);
+  const bool lc = l & c0, lm = l & !c0 & (k0 == BC_WALL), lo = l & !c0 & (k0 == BC_OUTFLOW);
+  const bool rc = r & c1, rm = r & !c1 & (k1 == BC_WALL), ro = r & !c1 & (k1 == BC_OUTFLOW);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    if constexpr (UNI) {
+      xm[i] = lc ? uni(K.ga[0][i]) : lm ? cur[mirror_x(i)] : lo ? cur[i] : xm[i];
+      xp[i] = rc ? uni(K.ga[1][i]) : rm ? cur[mirror_x(i)] : ro ? cur[i] : xp[i];
+    } else {
+      xm[i] = lc ? K.ga[0][i] : lm ? cur[mirror_x(i)] : lo ? cur[i] : xm[i];
+      xp[i] = rc ? K.ga[1][i] : rm ? cur[mirror_x(i)] : ro ? cur[i] : xp[i];
+    }
+  }
+}
+
 // f1 of row y at the lane's column from f0 rows y-1, y, y+1 (prev, cur, nxt),
 // rounded to the storage type (lanes 0 and 63: not meaningful, never used).
-template <bool XEDGE, class V>
+// SEL: the x ghosts as selects (ghost_x_select) instead of per-lane branches.
+template <bool XEDGE, class V, bool SEL = false>
 __device__ __forceinline__ void row_first(const KTConsts& K, const V& fi, const Lane2& L, int y,
                                           const double prev[9], const double cur[9], const double nxt[9],
                                           double t[9]) {
@@ -764,8 +806,12 @@ __device__ __forceinline__ void row_first(const KTConsts& K, const V& fi, const 
     xp[i] = shl1z(cur[i]);
   }
   if (XEDGE && !L.perx) {   // ghost_x reads no memory for non-periodic edges
-    if (L.x == 0) ghost_x<0>(K, fi, y, cur, xm);
-    if (L.x == K.nx - 1) ghost_x<1>(K, fi, y, cur, xp);
+    if constexpr (SEL) {
+      ghost_x_select<true>(K, L, y, cur, xm, xp);
+    } else {
+      if (L.x == 0) ghost_x<0>(K, fi, y, cur, xm);
+      if (L.x == K.nx - 1) ghost_x<1>(K, fi, y, cur, xp);
+    }
   }
   site_update(K, cur, xp, xm, nxt, prev, t);
 #pragma unroll
@@ -775,7 +821,7 @@ __device__ __forceinline__ void row_first(const KTConsts& K, const V& fi, const 
 // The second step of row y from f1 rows y-1, y, y+1 (held in the storage type,
 // or in double where a ghost row holds unrounded constants), stored by the
 // output lanes.
-template <bool XEDGE, class V, typename A, typename B, typename C>
+template <bool XEDGE, class V, typename A, typename B, typename C, bool SEL = false>
 __device__ __forceinline__ void row_second(const KTConsts& K, const V& fo, const Lane2& L, int y, const A p1[9],
                                            const B c1[9], const C n1[9]) {
   double prev[9], cur[9], nxt[9], xm[9], xp[9], out[9];
@@ -788,8 +834,12 @@ __device__ __forceinline__ void row_second(const KTConsts& K, const V& fo, const
     xp[i] = shl1z(cur[i]);
   }
   if (XEDGE && !L.perx) {
-    if (L.x == 0) ghost_x<0>(K, fo, y, cur, xm);
-    if (L.x == K.nx - 1) ghost_x<1>(K, fo, y, cur, xp);
+    if constexpr (SEL) {
+      ghost_x_select<true>(K, L, y, cur, xm, xp);
+    } else {
+      if (L.x == 0) ghost_x<0>(K, fo, y, cur, xm);
+      if (L.x == K.nx - 1) ghost_x<1>(K, fo, y, cur, xp);
+    }
   }
   site_update(K, cur, xp, xm, nxt, prev, out);
   if (L.out) fo.store9(y, L.vbo, out);
@@ -798,7 +848,7 @@ __device__ __forceinline__ void row_second(const KTConsts& K, const V& fo, const
 // y ghost row of f1 on edge E (2: below row 0, 3: above row ny-1) for a
 // non-periodic edge, from the f1 row next to it (as ghost_row forms it from the
 // stored f1 at the second step's time). x is the grid column the lane holds.
-template <int E, typename Q>
+template <int E, typename Q, bool UNI = false>
 __device__ __forceinline__ void ghost_row_f1(const KTConsts& K, int x, int ish, const Q src[9], double r[9]) {
   const int kind = K.kind[E];
   if (kind == BC_OUTFLOW) {
@@ -810,11 +860,16 @@ __device__ __forceinline__ void ghost_row_f1(const KTConsts& K, int x, int ish, 
   } else {
     const bool a = (kind == BC_INFLOW) || (x < ish);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) r[i] = a ? K.ga[E][i] : K.gb[E][i];
+    for (int i = 0; i < 9; ++i) {
+      if constexpr (UNI)
+        r[i] = a ? uni(K.ga[E][i]) : uni(K.gb[E][i]);
+      else
+        r[i] = a ? K.ga[E][i] : K.gb[E][i];
+    }
   }
   if (x < K.split[E]) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) r[i] = K.ga[E][i];
+    for (int i = 0; i < 9; ++i) r[i] = UNI ? uni(K.ga[E][i]) : K.ga[E][i];
   }
 }
 
@@ -1349,6 +1404,237 @@ __global__ __launch_bounds__(256) void k_init_adjoint(KTConsts K, const double* 
   }
 }
 
+// ------------------------------------------------------------------ three steps per pass
+
+// Three consecutive steps in one pass over an FP64 array: the two-step march with
+// a third stage. Lane j of a wavefront holds column X0 - 3 + j; f1 is right on
+// lanes 1..62, f2 on 2..61, and lanes 3..60 (58 columns) store f3. While f1 of
+// row y is computed, the march also computes f2 of row y-1 and f3 of row y-2
+// (stored), so an output tile [y0, y1) computes f1 on rows y0-2 .. y1+1 and f2
+// on rows y0-1 .. y1 from f0 rows y0-3 .. y1+2. As in the two-step march every
+// ghost of f1 and f2 is formed as a single step forms it from the stored state
+// (x ghosts through ghost_x; y ghosts of a non-periodic axis from the edge row
+// at that step's time index; a periodic y axis wraps its rows), so the result is
+// bitwise that of three single steps. HBM moves the 9 + 9 values of a site once
+// per three steps.
+
+// Row y of an axis of ny >= 3 rows with wrapping, for -3 <= y <= ny + 2.
+__device__ __forceinline__ int wrap_row(int y, int ny) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); }
+
+// One row of the march of a tile with no y ghost rows: fetch f0 row y+3 (F),
+// compute f1 of row y (N: f0 row y+1), f2 of row y-1 and f3 of row y-2 (stored);
+// shift the windows. rw(): the grid row of a march row (wrapped for a periodic
+// axis), yl the last f0 row the tile reads.
+template <bool XEDGE, class V>
+__device__ __forceinline__ void march3_row(const KTConsts& K, const V& fi, const V& fo, const Lane2& L, int y,
+                                           int yl, int ny, bool pery, double pd[9], double cd[9], double q0[9],
+                                           double q1[9], double r0[9], double r1[9], const double N[9],
+                                           double F[9]) {
+  static_assert(sizeof(Sto<V>) == 8, "three steps per pass run on FP64 arrays");
+  const int yf = min(y + 3, yl);
+  fi.raw9(pery ? wrap_row(yf, ny) : yf, L.vbx, F);
+  double t[9], u[9];
+  row_first<XEDGE, V, true>(K, fi, L, pery ? wrap_row(y, ny) : y, pd, cd, N, t);              // f1(y)
+  __builtin_amdgcn_sched_barrier(0);   // the updates one after the other (register pressure)
+  row_first<XEDGE, V, true>(K, fi, L, pery ? wrap_row(y - 1, ny) : y - 1, q0, q1, t, u);      // f2(y-1)
+  __builtin_amdgcn_sched_barrier(0);
+  row_second<XEDGE, V, double, double, double, true>(K, fo, L, y - 2, r0, r1, u);                                    // f3(y-2)
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    pd[i] = cd[i];
+    cd[i] = N[i];
+    q0[i] = q1[i];
+    q1[i] = t[i];
+    r0[i] = r1[i];
+    r1[i] = u[i];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// The march of an output tile [y0, y1) whose f0 rows y0-3 .. y1+2 all lie in the
+// grid, or wrap on a periodic y axis (no ghost rows): four priming rows, then
+// one row of every stage per f1 row.
+template <bool XEDGE, class V>
+__device__ __forceinline__ void march3_fast(const KTConsts& K, const V& fi, const V& fo, const Lane2& L, int y0,
+                                            int y1) {
+  const int ny = K.ny;
+  const bool pery = (K.kind[2] == BC_PERIODIC);
+  const int yl = y1 + 2;
+  auto rw = [&](int y) { return pery ? wrap_row(y, ny) : y; };
+  double pd[9], cd[9], N0[9], N1[9], N2[9], q0[9], q1[9], r0[9], r1[9], t[9];
+  const int ya = y0 - 2;   // first f1 row
+  fi.raw9(rw(ya - 1), L.vbx, pd);
+  fi.raw9(rw(ya), L.vbx, cd);
+  fi.raw9(rw(ya + 1), L.vbx, N0);
+  fi.raw9(rw(ya + 2), L.vbx, N1);
+  // f1 row ya (q0)
+  fi.raw9(rw(ya + 3), L.vbx, N2);
+  row_first<XEDGE, V, true>(K, fi, L, rw(ya), pd, cd, N0, q0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    pd[i] = cd[i];
+    cd[i] = N0[i];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // f1 row ya+1 (q1)
+  fi.raw9(rw(min(ya + 4, yl)), L.vbx, N0);
+  row_first<XEDGE, V, true>(K, fi, L, rw(ya + 1), pd, cd, N1, q1);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    pd[i] = cd[i];
+    cd[i] = N1[i];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // f1 row ya+2, f2 row ya+1 (r0)
+  fi.raw9(rw(min(ya + 5, yl)), L.vbx, N1);
+  row_first<XEDGE, V, true>(K, fi, L, rw(ya + 2), pd, cd, N2, t);
+  __builtin_amdgcn_sched_barrier(0);
+  row_first<XEDGE, V, true>(K, fi, L, rw(ya + 1), q0, q1, t, r0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    pd[i] = cd[i];
+    cd[i] = N2[i];
+    q0[i] = q1[i];
+    q1[i] = t[i];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // f1 row ya+3, f2 row ya+2 = y0 (r1)
+  fi.raw9(rw(min(ya + 6, yl)), L.vbx, N2);
+  row_first<XEDGE, V, true>(K, fi, L, rw(ya + 3), pd, cd, N0, t);
+  __builtin_amdgcn_sched_barrier(0);
+  row_first<XEDGE, V, true>(K, fi, L, rw(ya + 2), q0, q1, t, r1);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    pd[i] = cd[i];
+    cd[i] = N0[i];
+    q0[i] = q1[i];
+    q1[i] = t[i];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // rows y = y0+2 .. y1+1: f0 rows y+1, y+2 in flight in N1, N2; N0 free. The
+  // sets rotate with period three (the loop is unrolled by three).
+  int y = y0 + 2;
+  const int ye = y1 + 1;
+  for (; y + 2 <= ye; y += 3) {
+    march3_row<XEDGE>(K, fi, fo, L, y, yl, ny, pery, pd, cd, q0, q1, r0, r1, N1, N0);
+    march3_row<XEDGE>(K, fi, fo, L, y + 1, yl, ny, pery, pd, cd, q0, q1, r0, r1, N2, N1);
+    march3_row<XEDGE>(K, fi, fo, L, y + 2, yl, ny, pery, pd, cd, q0, q1, r0, r1, N0, N2);
+  }
+  for (; y <= ye; ++y) {   // 0-2 rows left: one code copy, the sets moved down
+    march3_row<XEDGE>(K, fi, fo, L, y, yl, ny, pery, pd, cd, q0, q1, r0, r1, N1, N0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      N1[i] = N2[i];
+      N2[i] = N0[i];
+    }
+  }
+}
+
+// The march of any output tile, one f0 row fetched per march row: on a periodic
+// y axis the rows wrap; otherwise f1 and f2 rows are clipped to the grid and
+// the f0, f1 and f2 ghost rows below row 0 and above row ny-1 are formed at
+// their own time indices (ish0 / ish1 / ish2: the shock edges' cells at steps
+// n, n+1, n+2). Used for the tiles march3_fast does not take.
+template <bool XEDGE, class V>
+__device__ __forceinline__ void march3_edge(const KTConsts& K, const V& fi, const V& fo, const Lane2& L, int y0,
+                                            int y1, int ish0_lo, int ish0_hi, int ish1_lo, int ish1_hi,
+                                            int ish2_lo, int ish2_hi) {
+  const int ny = K.ny;
+  const bool pery = (K.kind[2] == BC_PERIODIC);
+  auto rw = [&](int y) { return pery ? wrap_row(y, ny) : y; };
+  // f1 rows [a1, b1] and f2 rows [a2, b2] of the march (virtual rows when periodic)
+  const int a1 = pery ? y0 - 2 : max(y0 - 2, 0), b1 = pery ? y1 + 1 : min(y1 + 1, ny - 1);
+  const int a2 = pery ? y0 - 1 : max(y0 - 1, 0), b2 = pery ? y1 : min(y1, ny - 1);
+  const int ye = (!pery && b1 == ny - 1) ? ny + 1 : b1;   // the top edge needs two more rows
+  double pd[9], cd[9], q0[9], q1[9], r0[9], r1[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) q0[i] = q1[i] = r0[i] = r1[i] = 0.0;
+  if (pery || a1 > 0)
+    fi.load9(rw(a1 - 1), L.vbx, pd);
+  else
+    ghost_row<2, V, true>(K, fi, L.xs, L.vbx, ish0_lo, pd);
+  fi.load9(rw(a1), L.vbx, cd);
+  for (int y = a1; y <= ye; ++y) {
+    // f1 row y (q0, q1: f1 rows y-2, y-1; pd, cd: f0 rows y-1, y)
+    double nd[9], t[9], u[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) nd[i] = t[i] = u[i] = 0.0;
+    if (y <= b1) {
+      if (pery || y + 1 < ny)
+        fi.load9(rw(y + 1), L.vbx, nd);
+      else
+        ghost_row<3, V, true>(K, fi, L.xs, L.vbx, ish0_hi, nd);
+      row_first<XEDGE, V, true>(K, fi, L, rw(y), pd, cd, nd, t);
+    } else if (y == ny) {   // the f1 ghost above row ny-1 (not periodic)
+      ghost_row_f1<3, double, true>(K, L.xs, ish1_hi, q1, t);
+    }
+    // f2 row z = y-1 from f1 rows z-1 (the ghost below row 0 for z = 0), z, z+1
+    const int z = y - 1;
+    if (z >= a2 && z <= b2) {
+      if (!pery && z == 0) {
+        double g[9];
+        ghost_row_f1<2, double, true>(K, L.xs, ish1_lo, q1, g);
+        row_first<XEDGE, V, true>(K, fi, L, z, g, q1, t, u);
+      } else {
+        row_first<XEDGE, V, true>(K, fi, L, rw(z), q0, q1, t, u);
+      }
+    } else if (!pery && z == ny) {   // the f2 ghost above row ny-1
+      ghost_row_f1<3, double, true>(K, L.xs, ish2_hi, r1, u);
+    }
+    // f3 row w = y-2 from f2 rows w-1 (the ghost below row 0 for w = 0), w, w+1
+    const int w = y - 2;
+    if (w >= y0 && w < y1) {
+      if (!pery && w == 0) {
+        double g[9];
+        ghost_row_f1<2, double, true>(K, L.xs, ish2_lo, r1, g);
+        row_second<XEDGE, V, double, double, double, true>(K, fo, L, w, g, r1, u);
+      } else {
+        row_second<XEDGE, V, double, double, double, true>(K, fo, L, w, r0, r1, u);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      pd[i] = cd[i];
+      cd[i] = nd[i];
+      q0[i] = q1[i];
+      q1[i] = t[i];
+      r0[i] = r1[i];
+      r1[i] = u[i];
+    }
+  }
+}
+
+// Tiles in raster order, one block per tile when gridDim.x equals the tile count.
+// Arrays below 4 GiB, ny >= 3.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_step3(
+    KTConsts K, const double* __restrict__ fin, double* __restrict__ fout, int rows, int nstrips, int ntiles,
+    int ish0_lo, int ish0_hi, int ish1_lo, int ish1_hi, int ish2_lo, int ish2_hi) {
+  const View<double, 2> fi = make_view<double, 2>(K, fin), fo = make_view<double, 2>(K, fout);   // NT stores
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  for (int id = blockIdx.x; id < ntiles; id += gridDim.x) {
+    const int strip = id % nstrips, chunk = id / nstrips;
+    // the strip's first column, the same for the whole wavefront (scalar branches below)
+    const int X0 = __builtin_amdgcn_readfirstlane((strip * wpb + (int)(threadIdx.x >> 6)) * 58);
+    if (X0 >= K.nx) continue;   // whole wavefront beyond the grid
+    const int y0 = chunk * rows;
+    const int y1 = min(y0 + rows, K.ny);
+    const Lane2 L = make_lane2<double>(K, X0, lane, 3);
+    // the lanes hold columns X0-3 .. X0+60: x-edge logic when 0 or nx-1 is among them
+    const bool xedge = (X0 == 0) || (X0 + 61 >= K.nx);
+    // the prefetching march for strips away from the x edges whose rows need no
+    // y ghosts; the row-by-row march for the rest (x-edge strips, y-edge tiles)
+    const bool fast = !xedge && ((K.kind[2] == BC_PERIODIC) || (y0 >= 3 && y1 <= K.ny - 3));
+    const KTConsts& KM = kernarg_consts();   // K itself, for the march loops
+    if (fast)
+      march3_fast<false>(KM, fi, fo, L, y0, y1);
+    else if (xedge)
+      march3_edge<true>(KM, fi, fo, L, y0, y1, ish0_lo, ish0_hi, ish1_lo, ish1_hi, ish2_lo, ish2_hi);
+    else
+      march3_edge<false>(KM, fi, fo, L, y0, y1, ish0_lo, ish0_hi, ish1_lo, ish1_hi, ish2_lo, ish2_hi);
+  }
+}
+
 // ------------------------------------------------------------------ batched
 
 using WorkItem = LbktWorkItem;
@@ -1426,27 +1712,6 @@ __device__ __forceinline__ void march2_ny4(const KTConsts& K, const V& fi, const
   row_second<XEDGE>(K, fo, L, 2, q1, q2, q3);
   __builtin_amdgcn_sched_barrier(0);
   row_second<XEDGE>(K, fo, L, 3, q2, q3, q0);
-}
-
-// The x ghosts of a row for the lanes at a non-periodic x edge, as ghost_x forms
-// them (x edges are walls, inflow or outflow here, periodic ones are handled by
-// the lanes' wrapped columns), written as selects instead of branches: the lane
-// holding column 0 takes its x-1 neighbour xm from the edge, the lane holding
-// column nx-1 its x+1 neighbour xp.
-__device__ __forceinline__ void ghost_x_select(const KTConsts& K, const Lane2& L, int y, const double cur[9],
-                                               double xm[9], double xp[9]) {
-  // the edge's kind and split are read first and combined without short-circuit
-  // evaluation, so no per-lane branch guards the reads
-  const int k0 = K.kind[0], k1 = K.kind[1], s0 = K.split[0], s1 = K.split[1];
-  const bool l = (L.x == 0), r = (L.x == K.nx - 1);
-  const bool c0 = (k0 == BC_INFLOW) | (y < s0), c1 = (k1 == BC_INFLOW) | (y < s1);
-  const bool lc = l & c0, lm = l & !c0 & (k0 == BC_WALL), lo = l & !c0 & (k0 == BC_OUTFLOW);
-  const bool rc = r & c1, rm = r & !c1 & (k1 == BC_WALL), ro = r & !c1 & (k1 == BC_OUTFLOW);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    xm[i] = lc ? K.ga[0][i] : lm ? cur[mirror_x(i)] : lo ? cur[i] : xm[i];
-    xp[i] = rc ? K.ga[1][i] : rm ? cur[mirror_x(i)] : ro ? cur[i] : xp[i];
-  }
 }
 
 // One step of row y of the strip's state (rows y-1, y, y+1 = pt, ct, nt, held in
@@ -1703,8 +1968,9 @@ static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 
 struct Tile {
   int bx, rows, blocks;
-  int steps;   // time steps per pass of lb_run: 1, or 2 (the two-step kernel)
-  bool user;   // shape given by the caller (else the default, per kernel)
+  int steps;        // time steps per pass of lb_run: 1, 2 or 3 (the two- and three-step kernels)
+  bool user;        // shape given by the caller (else the default, per kernel)
+  bool steps_auto;  // steps not given: lb_run takes three per pass where that kernel runs
 };
 
 // Default launch shape: 256 x 16 tiles on large grids; on smaller grids the
@@ -1739,6 +2005,25 @@ static void default_tile2(int nx, int ny, lb_prec prec, int* bx, int* rows) {
 
 void lbkt_default_tile2(int nx, int ny, lb_prec prec, int* bx, int* rows) { default_tile2(nx, ny, prec, bx, rows); }
 
+// Default launch shape of the three-step pass (FP64): 256 threads (4 x 58
+// columns) by 11 rows, the fastest measured on the 8192 x 2048 grid among
+// 128 / 256 threads and 11-32 rows; shrunk on smaller grids as the two-step shape.
+static void default_tile3(int nx, int ny, int* bx, int* rows) {
+  auto ntiles = [&](int b, int r) { return cdiv(cdiv(nx, 58), b / 64) * cdiv(ny, r); };
+  int b = 256, r = 11;
+  while (ntiles(b, r) < 1024 && r > 2) r = std::max(2, r / 2);
+  while (ntiles(b, r) < 1024 && b > 64) b /= 2;
+  if (ntiles(b, r) < 1024) r = 1;
+  *bx = b;
+  *rows = std::min(r, ny);
+}
+
+// The three-step kernel runs on FP64 arrays below 4 GiB with ny >= 3 (its rows
+// wrap with one addition on a periodic axis).
+static bool three_ok(const lb_grid* g, lb_prec prec) {
+  return prec == LB_F64 && g->ny >= 3 && !wide(g, elem_size(prec));
+}
+
 static lb_status resolve_tile(const lb_tile* tile, int nx, int ny, Tile* t) {
   int b, r, nb = 0;
   default_tile(nx, ny, &b, &r);
@@ -1752,13 +2037,14 @@ static lb_status resolve_tile(const lb_tile* tile, int nx, int ny, Tile* t) {
   if (r < 1) return fail(LB_EINVAL, "tile rows must be >= 1");
   if (nb < 0) return fail(LB_EINVAL, "tile blocks must be >= 0");
   const int sp = tile ? tile->steps : 0;
-  if (sp < 0 || sp > 2) return fail(LB_EINVAL, "tile steps must be 0, 1 or 2");
+  if (sp < 0 || sp > 3) return fail(LB_EINVAL, "tile steps must be 0, 1, 2 or 3");
   t->bx = b;
   t->rows = std::min(r, ny);
   t->blocks = nb;
   t->user = user;
   // two steps per pass need two rows (the f1 window is primed with two rows)
   t->steps = (ny < 2) ? 1 : (sp == 0 ? 2 : sp);
+  t->steps_auto = (sp == 0);
   return LB_OK;
 }
 
@@ -1824,14 +2110,65 @@ static lb_status launch_step2(const lb_grid* g, const KTConsts& K, lb_prec prec,
   return LB_OK;
 }
 
+// Three steps f_out = S(S(S(f_in))) at time indices step .. step+2 in one pass
+// (FP64 arrays below 4 GiB, ny >= 3).
+static lb_status launch_step3(const lb_grid* g, const KTConsts& K, const void* fin, void* fout, int64_t step,
+                              const Tile& t, hipStream_t st) {
+  int bx = t.bx, rows = t.rows;
+  if (!t.user) default_tile3(g->nx, g->ny, &bx, &rows);
+  const int wpb = bx / 64;
+  const int nstrips = (int)cdiv(cdiv(g->nx, 58), wpb);   // 58 output columns per wavefront
+  const int64_t ntiles64 = (int64_t)nstrips * cdiv(g->ny, rows);
+  if (ntiles64 > 0x7fffffff) return fail(LB_EINVAL, "grid too large for one launch");
+  const int ntiles = (int)ntiles64;
+  const int nblocks = (t.blocks > 0 && t.blocks < ntiles) ? t.blocks : ntiles;
+  int ish[6];
+  for (int k = 0; k < 3; ++k) {
+    ish[2 * k] = shock_cells(g, 2, step + k);
+    ish[2 * k + 1] = shock_cells(g, 3, step + k);
+  }
+  hipLaunchKernelGGL(k_step3, dim3(nblocks), dim3(bx), 0, st, K, (const double*)fin, (double*)fout, rows, nstrips,
+                     ntiles, ish[0], ish[1], ish[2], ish[3], ish[4], ish[5]);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
+// Time steps per pass of lb_run for a resolved tile: by default 3 for FP64
+// arrays where the three-step kernel runs and ny >= 32, else the tile's (1 or
+// 2); an explicit 3 where that kernel does not run is LB_EUNSUPPORTED. On fewer
+// rows most tiles lie at a y edge and take the row-by-row march, which made the
+// paper's 4-row Riemann grids slower than two steps per pass (4.3 vs 3.0 us per
+// step through a graph on the 200 x 4 Sod grid).
+static lb_status pass_steps(const lb_grid* g, lb_prec prec, const Tile& t, int* steps) {
+  if (t.steps == 3 && !three_ok(g, prec))
+    return fail(LB_EUNSUPPORTED, "three steps per pass run on FP64 arrays below 4 GiB with ny >= 3");
+  *steps = (t.steps_auto && three_ok(g, prec) && g->ny >= 32) ? 3 : t.steps;
+  return LB_OK;
+}
+
 // nsteps ping-pong steps from fa (result in fa when nsteps is even, else in fb).
 // With two steps per pass, a pass also swaps the buffers once, so the pairs must
 // be an even number: 2p steps in p passes with p even, and the remaining 0..3
-// steps one per launch, first.
+// steps one per launch, first. A three-step pass swaps once for an odd number of
+// steps, so n = 3p + r runs r = 0..2 single steps, then p three-step passes.
 static lb_status launch_steps(const lb_grid* g, const KTConsts& K, lb_prec prec, void* fa, void* fb, int64_t step0,
                               int nsteps, const Tile& t, hipStream_t st) {
+  int sp;
+  lb_status s0 = pass_steps(g, prec, t, &sp);
+  if (s0) return s0;
+  if (sp == 3) {
+    const int triples = nsteps / 3;
+    int64_t n = step0;
+    int k = 0;
+    lb_status s;
+    for (int j = 0; j < nsteps - 3 * triples; ++j, ++k, ++n)
+      if ((s = launch_step(g, K, prec, (k % 2 == 0) ? fa : fb, (k % 2 == 0) ? fb : fa, n, t, st))) return s;
+    for (int j = 0; j < triples; ++j, ++k, n += 3)
+      if ((s = launch_step3(g, K, (k % 2 == 0) ? fa : fb, (k % 2 == 0) ? fb : fa, n, t, st))) return s;
+    return LB_OK;
+  }
   // a large array's two-step window (tile rows + 4 rows) must stay below 4 GiB
-  const bool two = (t.steps == 2) && (!wide(g, elem_size(prec)) || wide_max_rows(g, elem_size(prec)) >= 3);
+  const bool two = (sp == 2) && (!wide(g, elem_size(prec)) || wide_max_rows(g, elem_size(prec)) >= 3);
   const int pairs = two ? (nsteps / 2) & ~1 : 0;
   const int singles = nsteps - 2 * pairs;
   int64_t n = step0;
@@ -1949,8 +2286,10 @@ extern "C" lb_status lb_run(const lb_grid* g, int32_t prec_code, void* fa, void*
   build_consts(g, &K);
   hipStream_t st = (hipStream_t)stream;
   if (!use_graph || st == nullptr || nsteps == 0) return launch_steps(g, K, prec, fa, fb, step0, nsteps, t, st);
+  int sp;
+  if ((s = pass_steps(g, prec, t, &sp))) return s;
   const std::string key =
-      run_key(g, prec, fa, fb, step0, nsteps, t.bx, (t.rows * 1000003 + t.blocks) * 3 + t.steps, stream);
+      run_key(g, prec, fa, fb, step0, nsteps, t.bx, (t.rows * 1000003 + t.blocks) * 4 + sp, stream);
   std::lock_guard<std::mutex> lock(g_graph_mu);
   for (auto& e : g_graphs)
     if (e.key == key) return launch_exec(e.exec, e.done, st);
@@ -2686,16 +3025,20 @@ extern "C" lb_status lb_autotune(const lb_grid* g, int32_t prec_code, void* fa, 
   lb_tile bt = {256, 16, 0, 0};
   KTConsts K;
   build_consts(g, &K);
-  // both kernels lb_run can use: one step per launch, and two per pass (ny >= 2)
-  for (int sp = 1; sp <= (g->ny >= 2 ? 2 : 1); ++sp)
+  // every kernel lb_run can use: one step per launch, two per pass (ny >= 2), and
+  // three per pass (FP64 arrays below 4 GiB, ny >= 3)
+  const int spmax = three_ok(g, prec) ? 3 : (g->ny >= 2 ? 2 : 1);
+  for (int sp = 1; sp <= spmax; ++sp)
     for (int bi = 0; bi < 3; ++bi)
       for (int ri = 0; ri < 9; ++ri)
         for (int ni = 0; ni < 3; ++ni) {
           const int bx = bxs[bi], rows = std::min(rws[ri], g->ny);
           if (ri > 0 && rows == std::min(rws[ri - 1], g->ny)) continue;
-          const Tile t = {bx, rows, nbs[ni], sp, true};
+          const Tile t = {bx, rows, nbs[ni], sp, true, false};
           auto launch = [&](const void* in, void* out) {
-            return sp == 1 ? launch_step(g, K, prec, in, out, 0, t, st) : launch_step2(g, K, prec, in, out, 0, t, st);
+            return sp == 1   ? launch_step(g, K, prec, in, out, 0, t, st)
+                   : sp == 2 ? launch_step2(g, K, prec, in, out, 0, t, st)
+                             : launch_step3(g, K, in, out, 0, t, st);
           };
           // warm-up launch, then reps timed launches: on a stream, captured in a
           // graph and timed as one replay (as lb_run with use_graph runs them;

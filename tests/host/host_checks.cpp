@@ -308,8 +308,10 @@ static void check_early_errors() {
   CHECK(lb_run(&g, LB_F32, a, b, 0, -1, 0, nullptr, nullptr) == LB_EINVAL, "nsteps");
   lb_tile t = {96, 4, 0, 0};
   CHECK(lb_run(&g, LB_F32, a, b, 0, 4, 0, &t, nullptr) == LB_EINVAL, "tile width");
-  t = {256, 4, 0, 3};
+  t = {256, 4, 0, 4};
   CHECK(lb_run(&g, LB_F32, a, b, 0, 4, 0, &t, nullptr) == LB_EINVAL, "tile steps");
+  t = {256, 4, 0, 3};   // three steps per pass: FP64 arrays only
+  CHECK(lb_run(&g, LB_F32, a, b, 0, 4, 0, &t, nullptr) == LB_EUNSUPPORTED, "three steps on FP32");
   CHECK(lb_init(&g, LB_F64, nullptr, nullptr, nullptr, nullptr, a, nullptr) == LB_EINVAL, "init fields");
   CHECK(lb_moments(&g, LB_F64, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) == LB_EINVAL, "moments f");
   CHECK(lb_invariants(&g, LB_F64, a, nullptr, nullptr) == LB_EINVAL, "invariants out");

@@ -115,14 +115,21 @@ def test_batched_problem_over_4_gib_rejected():
 
 
 def test_tile_steps_validated_before_launch():
-    """lb_tile.steps (time steps per pass of lb_run) must be 0, 1 or 2."""
+    """lb_tile.steps (time steps per pass of lb_run) must be 0, 1, 2 or 3, and 3 runs
+    on FP64 arrays with at least 3 rows only (LB_EUNSUPPORTED otherwise)."""
     L = _lib.lib()
     g = _grid().c()
     a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)   # never dereferenced
-    for steps, want in ((3, -1), (-1, -1)):
+    for steps, want in ((4, -1), (-1, -1)):
         t = _lib.LbTile(0, 0, 0, steps)
         st = L.lb_run(ctypes.byref(g), 0, a, b, 0, 4, 0, ctypes.byref(t), None)
         assert st == want and b"steps" in L.lb_last_error()
+    t = _lib.LbTile(0, 0, 0, 3)
+    assert L.lb_run(ctypes.byref(g), 1, a, b, 0, 4, 0, ctypes.byref(t), None) == -7   # FP32 storage
+    assert b"three steps" in L.lb_last_error()
+    g2 = _grid(ny=2).c()
+    assert L.lb_run(ctypes.byref(g2), 0, a, b, 0, 4, 0, ctypes.byref(t), None) == -7   # two rows
+    assert b"three steps" in L.lb_last_error()
 
 
 def test_alias_and_alignment_rejected_before_launch():
