@@ -102,6 +102,9 @@ __device__ __forceinline__ double recip(double x) {
 // Macroscopic fields, Eqs. (e4), (e5), (e7): rho, u = j/rho, T = (E/rho - u.u)/b.
 struct Prim { double rho, ux, uy, T, rinv, usq; };
 
+// RCP: the quotients as products with 1/rho (recip) and the host-rounded 1/b,
+// within two ulps of the corrected ones (the kernels with FP32 storage; see site_update).
+template <bool RCP = false>
 __device__ inline Prim moments9(const KTConsts& K, const double f[9]) {
   const double s14 = (f[1] + f[2]) + (f[3] + f[4]);
   const double s58 = (f[5] + f[6]) + (f[7] + f[8]);
@@ -112,32 +115,48 @@ __device__ inline Prim moments9(const KTConsts& K, const double f[9]) {
   Prim P;
   P.rho = rho;
   P.rinv = recip(rho);
-  P.ux = div_cr(jx, rho, P.rinv);
-  P.uy = div_cr(jy, rho, P.rinv);
-  P.usq = fma(P.ux, P.ux, P.uy * P.uy);
-  P.T = div_cr(div_cr(E, rho, P.rinv) - P.usq, K.bval, K.inv_b);
+  if constexpr (RCP) {
+    P.ux = jx * P.rinv;
+    P.uy = jy * P.rinv;
+    P.usq = fma(P.ux, P.ux, P.uy * P.uy);
+    P.T = (E * P.rinv - P.usq) * K.inv_b;
+  } else {
+    P.ux = div_cr(jx, rho, P.rinv);
+    P.uy = div_cr(jy, rho, P.rinv);
+    P.usq = fma(P.ux, P.ux, P.uy * P.uy);
+    P.T = div_cr(div_cr(E, rho, P.rinv) - P.usq, K.bval, K.inv_b);
+  }
   return P;
 }
 
 // Group coefficients of Eqs. (e17)-(e18) at (T, usq).
 struct Coef { double A0, A1, A5, B1, B5; };
 
+template <bool RCP = false>
 __host__ __device__ inline Coef coef(const KTConsts& K, double T, double usq) {
   Coef C;
   C.A0 = K.a0T * T;
-  C.A1 = div_cr(fma(K.k1u, usq, fma(K.k1T, T, -K.c2sq)), K.k1d, K.r1d);
-  C.A5 = div_cr(fma(K.k5u, usq, fma(K.k5T, T, -K.c1sq)), K.k5d, K.r5d);
-  C.B1 = div_cr(fma(K.bT, T, usq) - K.c2sq, K.b1d, K.rb1d);
-  C.B5 = div_cr(fma(K.bT, T, usq) - K.c1sq, K.b5d, K.rb5d);
+  if constexpr (RCP) {
+    C.A1 = fma(K.k1u, usq, fma(K.k1T, T, -K.c2sq)) * K.r1d;
+    C.A5 = fma(K.k5u, usq, fma(K.k5T, T, -K.c1sq)) * K.r5d;
+    C.B1 = (fma(K.bT, T, usq) - K.c2sq) * K.rb1d;
+    C.B5 = (fma(K.bT, T, usq) - K.c1sq) * K.rb5d;
+  } else {
+    C.A1 = div_cr(fma(K.k1u, usq, fma(K.k1T, T, -K.c2sq)), K.k1d, K.r1d);
+    C.A5 = div_cr(fma(K.k5u, usq, fma(K.k5T, T, -K.c1sq)), K.k5d, K.r5d);
+    C.B1 = div_cr(fma(K.bT, T, usq) - K.c2sq, K.b1d, K.rb1d);
+    C.B5 = div_cr(fma(K.bT, T, usq) - K.c1sq, K.b5d, K.rb5d);
+  }
   return C;
 }
 
 // Equilibrium, Eq. (e16): f_i^eq = rho (A_i + B_i (v_i.u) + D_i (v_i.u)^2).
 // Axis planes: v.u = -/+ c1 ux (1, 3), -/+ c1 uy (2, 4);
 // diagonal planes: v.u = -/+ s (ux+uy) (5, 7), +/- s (ux-uy) (6, 8).
+template <bool RCP = false>
 __host__ __device__ inline void feq9(const KTConsts& K, double rho, double ux, double uy, double T,
                                      double usq, double fe[9]) {
-  const Coef C = coef(K, T, usq);
+  const Coef C = coef<RCP>(K, T, usq);
   const double ex = K.c1 * ux, ey = K.c1 * uy;
   const double dp = K.s * (ux + uy), dm = K.s * (ux - uy);
   const double px = fma(K.d1 * ex, ex, C.A1);
@@ -191,14 +210,20 @@ __host__ __device__ __forceinline__ double plane_update(const KTConsts& K, int i
 }
 
 // One site of the step: centre values c, neighbours at x+dx, x-dx, y+dy, y-dy.
+// RCP (the kernels with FP32 storage): quotients as products with reciprocals,
+// within two ulps of the corrected ones, far below the storage's rounding (FP32
+// two-step pass 2%, the batched four-step pass 5% faster); the FP64-storage
+// kernels keep the corrected quotients of the oracle's divisions. Every kernel of
+// one storage type takes the same form, so they agree bitwise.
+template <bool RCP = false>
 __device__ __forceinline__ void site_update(const KTConsts& K, const double c[9], const double xp[9],
                                                      const double xm[9], const double yp[9], const double ym[9],
                                                      double out[9]) {
-  const Prim P = moments9(K, c);
+  const Prim P = moments9<RCP>(K, c);
   // f^eq / tau, with 1/tau applied to rho once instead of to each f_i^eq (the
   // equilibrium is linear in rho; exact for tau = 1)
   double fe[9];
-  feq9(K, P.rho * K.inv_tau, P.ux, P.uy, P.T, P.usq, fe);
+  feq9<RCP>(K, P.rho * K.inv_tau, P.ux, P.uy, P.T, P.usq, fe);
 #pragma unroll
   for (int i = 0; i < 9; ++i) out[i] = plane_update(K, i, fe[i], c[i], xp[i], xm[i], yp[i], ym[i]);
 }

@@ -575,7 +575,7 @@ __device__ __forceinline__ void row_update(const KTConsts& K, const V& fi, const
     if (L.x == 0) ghost_x<0>(K, fi, y, cur, xm);
     if (L.x == K.nx - 1) ghost_x<1>(K, fi, y, cur, xp);
   }
-  site_update(K, cur, xp, xm, nxt, prev, out);
+  site_update<sizeof(Sto<V>) == 4>(K, cur, xp, xm, nxt, prev, out);
   // Lanes past nx store too, into the row's padding columns (x < pitch): no
   // result reads them, and an unmasked store keeps the compiler's wait counts
   // from having to cover a path on which the stores were skipped.
@@ -813,7 +813,7 @@ __device__ __forceinline__ void row_first(const KTConsts& K, const V& fi, const 
       if (L.x == K.nx - 1) ghost_x<1>(K, fi, y, cur, xp);
     }
   }
-  site_update(K, cur, xp, xm, nxt, prev, t);
+  site_update<sizeof(Sto<V>) == 4>(K, cur, xp, xm, nxt, prev, t);
 #pragma unroll
   for (int i = 0; i < 9; ++i) t[i] = (double)(Sto<V>)t[i];
 }
@@ -841,7 +841,7 @@ __device__ __forceinline__ void row_second(const KTConsts& K, const V& fo, const
       if (L.x == K.nx - 1) ghost_x<1>(K, fo, y, cur, xp);
     }
   }
-  site_update(K, cur, xp, xm, nxt, prev, out);
+  site_update<sizeof(Sto<V>) == 4>(K, cur, xp, xm, nxt, prev, out);
   if (L.out) fo.store9(y, L.vbo, out);
 }
 
@@ -1734,7 +1734,7 @@ __device__ __forceinline__ void ny4_state_step_row(const KTConsts& K, const V& f
     xp[i] = shl1z(c[i]);
   }
   if constexpr (XEDGE) ghost_x_select(K, L, y, c, xm, xp);
-  site_update(K, c, xp, xm, n, p, out);
+  site_update<sizeof(Sto<V>) == 4>(K, c, xp, xm, n, p, out);
   if constexpr (STORE) {
     if (L.out) f.store9(y, L.vbo, out);
   } else {
