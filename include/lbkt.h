@@ -120,7 +120,7 @@ typedef struct {
  * the XCDs in bands), each looping over tiles. All zero (or a NULL tile) = the
  * default: 256 x 32 tiles, one block per tile, shrunk on small grids (rows down
  * to 2, then columns) to give at least 1024 tiles; the two-step pass takes at
- * most 11 rows (double) or 24 rows (float) by default, the three-step pass 11
+ * most 11 rows (double) or 23 rows (float) by default, the three-step pass 11
  * rows. In the two-step pass a wavefront of 64 threads produces 60 columns, in
  * the three-step pass 58, so a tile is block_x / 64 * 60 (58) columns wide. */
 typedef struct {

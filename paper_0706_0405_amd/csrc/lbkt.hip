@@ -1986,8 +1986,9 @@ static void default_tile(int nx, int ny, int* bx, int* rows, int min_tiles = 102
 }
 
 // Default launch shape of the two-step pass: 256 threads (4 x 60 columns) by
-// 11 rows (double) or 24 rows (float), the fastest measured on the 8192 x 2048
-// grid; on smaller grids the rows shrink (down to 2), then the columns, then
+// 11 rows (double) or 23 rows (float), the fastest measured on the 8192 x 2048
+// grid (float, five interleaved rounds: 23 rows 115.6, 22 rows 115.3, 24 rows
+// 114.7, 20 rows 114.8 GLUPS); on smaller grids the rows shrink (down to 2), then the columns, then
 // the rows to 1, until there are at least 1024 tiles (on small grids
 // parallelism outweighs the extra first-step rows of a short tile; measured on
 // the paper's 200x4 .. 960x240 configurations against the autotuner).
@@ -1995,7 +1996,7 @@ static void default_tile2(int nx, int ny, lb_prec prec, int* bx, int* rows) {
   auto ntiles = [&](int b, int r) {
     return cdiv(cdiv(nx, 60), b / 64) * cdiv(ny, r);
   };
-  int b = 256, r = prec == LB_F64 ? 11 : 24;
+  int b = 256, r = prec == LB_F64 ? 11 : 23;
   while (ntiles(b, r) < 1024 && r > 2) r = std::max(2, r / 2);
   while (ntiles(b, r) < 1024 && b > 64) b /= 2;
   if (ntiles(b, r) < 1024) r = 1;

@@ -350,42 +350,43 @@ def test_roofline_grid_one_step_sampled_rows():
         torch.cuda.empty_cache()
 
 
-def test_roofline_grid_two_step_passes_sampled_rows():
-    """8192 x 2048 through lb_run as the benchmark runs it (two steps per pass, default
-    tiles of 11 rows in double and 24 in float storage): 4 steps from a seeded random
-    state, rows at tile edges and both y edges against the oracle, which computes at
-    each step the rows the sampled ones depend on (the state rounded to the storage
-    type after every step, as a stored step rounds it)."""
+@pytest.mark.parametrize("prec,spp", [("f64", 3), ("f64", 2), ("f32", 2)])
+def test_roofline_grid_passes_sampled_rows(prec, spp):
+    """8192 x 2048 through lb_run as the benchmark runs it (three steps per pass in
+    double storage, two in float; default tiles of 11 rows in double and 23 in float
+    storage) and two per pass in double: 6 steps from a seeded random state, rows at
+    tile edges and both y edges against the oracle, which computes at each step the
+    rows the sampled ones depend on (the state rounded to the storage type after
+    every step, as a stored step rounds it)."""
     lb = _lb()
     cfg = P.roofline_grid()
     g = lb.Grid.from_workload(cfg)
     pb = scheme.Problem.from_dict(cfg)
     raw = P.random_distributions(g.nx, g.ny, seed=23)
-    rows = [0, 1, 10, 11, 12, 22, 23, 24, 25, 1023, 1024, 2039, 2040, 2046, 2047]
-    nsteps = 4
-    for prec in ("f64", "f32"):
-        say("case roofline two-step", prec)
-        dt = torch.float64 if prec == "f64" else torch.float32
-        src = torch.tensor(raw, dtype=dt)
-        fa = lb.empty(g, prec, DEV)
-        fa[:, :, :g.nx] = src.to(DEV)
-        fb = lb.empty(g, prec, DEV)
-        out = lb.run(g, fa, fb, nsteps, prec=prec, steps_per_pass=2)
-        got = out[:, rows, :g.nx].cpu().to(F64)
-        del fa, fb, out
-        torch.cuda.empty_cache()
-        cur = src.to(F64)
-        for k in range(nsteps):
-            reach = nsteps - 1 - k   # rows within this distance of a sampled row are needed
-            need = sorted({min(max(r + d, 0), g.ny - 1) for r in rows for d in range(-reach, reach + 1)})
-            nxt = torch.zeros_like(cur)
-            nxt[:, need] = scheme.step_rows(pb, cur, k, need).to(dt).to(F64)
-            cur = nxt
-        want = cur[:, rows]
-        err = float(((got - want).abs() / want.abs().max()).max())
-        say("roofline two-step", prec, "max rel err", err)
-        assert torch.isfinite(got).all()
-        assert err < (1e-12 if prec == "f64" else 5e-7)
+    rows = [0, 1, 2, 10, 11, 12, 22, 23, 24, 46, 1023, 2045, 2046, 2047]
+    nsteps = 6
+    say("case roofline passes", prec, spp)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    src = torch.tensor(raw, dtype=dt)
+    fa = lb.empty(g, prec, DEV)
+    fa[:, :, :g.nx] = src.to(DEV)
+    fb = lb.empty(g, prec, DEV)
+    out = lb.run(g, fa, fb, nsteps, prec=prec, steps_per_pass=spp)
+    got = out[:, rows, :g.nx].cpu().to(F64)
+    del fa, fb, out
+    torch.cuda.empty_cache()
+    cur = src.to(F64)
+    for k in range(nsteps):
+        reach = nsteps - 1 - k   # rows within this distance of a sampled row are needed
+        need = sorted({min(max(r + d, 0), g.ny - 1) for r in rows for d in range(-reach, reach + 1)})
+        nxt = torch.zeros_like(cur)
+        nxt[:, need] = scheme.step_rows(pb, cur, k, need).to(dt).to(F64)
+        cur = nxt
+    want = cur[:, rows]
+    err = float(((got - want).abs() / want.abs().max()).max())
+    say("roofline passes", prec, spp, "max rel err", err)
+    assert torch.isfinite(got).all()
+    assert err < (1e-12 if prec == "f64" else 5e-7)
 
 
 def test_uniform_inflow_is_stationary():
