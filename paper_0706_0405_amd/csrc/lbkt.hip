@@ -249,6 +249,10 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 #else
 #define LB_STEP_ATTR
 #endif
+// waves per SIMD asked of the float one-step kernel below 4 GiB (its 168 VGPRs fit 3)
+#ifndef LB_STEP_F32_WAVES
+#define LB_STEP_F32_WAVES 3
+#endif
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, LB_RSRC_WORD3);
@@ -668,6 +672,20 @@ __device__ __forceinline__ void march(const KTConsts& K, const V& fi, const V& f
   }
 }
 
+// The grid constants of a kernel whose first argument is its KTConsts (offset 0
+// of the kernel-argument segment), re-read through a pointer that the compiler
+// cannot see through. Loads through it stay scalar and invariant (constant
+// address space), so the register allocator re-issues them (s_load) where the
+// march loops run short of SGPRs, instead of spilling the ~70 SGPRs of constants
+// to VGPR lanes and reloading them with v_readlane, which are VALU instructions
+// (float-storage two-step loop: 1308 instead of 1479 VALU instructions per
+// three rows).
+__device__ __forceinline__ const KTConsts& kernarg_consts() {
+  auto kp = (const __attribute__((address_space(4))) KTConsts*)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(kp));
+  return *(const KTConsts*)kp;
+}
+
 // Block index -> (strip, chunk). With xcd_map, the blocks that the hardware
 // deals round-robin to one XCD (ids congruent mod 8) get one contiguous band of
 // the (chunk, strip) raster, so x- and y-adjacent tiles share that XCD's L2.
@@ -687,7 +705,9 @@ __device__ __forceinline__ void tile_of_block(int id, int nstrips, int nblocks, 
 // of 8 whenever xcd_map is set, so every tile of a block stays in its XCD's band.
 // WIDE: arrays of 4 GiB and more, addressed through ViewG (64-bit addresses).
 template <typename S, bool WIDE>
-__global__ __launch_bounds__(256) LB_STEP_ATTR void k_step(KTConsts K, const S* __restrict__ fin,
+__global__ __launch_bounds__(256) LB_STEP_ATTR
+    __attribute__((amdgpu_waves_per_eu(sizeof(S) == 4 && !WIDE ? LB_STEP_F32_WAVES : 1))) void k_step(KTConsts K,
+                                                                                           const S* __restrict__ fin,
                                                            S* __restrict__ fout, int rows, int nstrips, int ntiles,
                                                            int xcd_map, int ish_lo, int ish_hi) {
   const View<S> fi0 = make_view<S>(K, fin), fo0 = make_view<S>(K, fout);
@@ -700,17 +720,18 @@ __global__ __launch_bounds__(256) LB_STEP_ATTR void k_step(KTConsts K, const S* 
     const int y0 = chunk * rows;
     const int y1 = min(y0 + rows, K.ny);
     const Lane L = make_lane<S>(K, xw0, lane);
+    const KTConsts& KM = kernarg_consts();   // K itself, for the march loops
     if constexpr (WIDE) {
       const ViewG<S> fi = make_view_g<S>(K, fin, y0, y1), fo = make_view_g<S>(K, fout, y0, y1);
       if (xw0 == 0 || xw0 + 64 >= K.nx)
-        march<true>(K, fi, fo, L, y0, y1, ish_lo, ish_hi);
+        march<true>(KM, fi, fo, L, y0, y1, ish_lo, ish_hi);
       else
-        march<false>(K, fi, fo, L, y0, y1, ish_lo, ish_hi);
+        march<false>(KM, fi, fo, L, y0, y1, ish_lo, ish_hi);
     } else {
       if (xw0 == 0 || xw0 + 64 >= K.nx)
-        march<true>(K, fi0, fo0, L, y0, y1, ish_lo, ish_hi);
+        march<true>(KM, fi0, fo0, L, y0, y1, ish_lo, ish_hi);
       else
-        march<false>(K, fi0, fo0, L, y0, y1, ish_lo, ish_hi);
+        march<false>(KM, fi0, fo0, L, y0, y1, ish_lo, ish_hi);
     }
   }
 }
@@ -1021,20 +1042,6 @@ __device__ __forceinline__ void march2(const KTConsts& K, const V& fi, const V& 
       ghost_row_f1<3>(K, L.xs, ish2_hi, q1, g);
     row_second<XEDGE>(K, fo, L, ny - 1, q0, q1, g);
   }
-}
-
-// The grid constants of a kernel whose first argument is its KTConsts (offset 0
-// of the kernel-argument segment), re-read through a pointer that the compiler
-// cannot see through. Loads through it stay scalar and invariant (constant
-// address space), so the register allocator re-issues them (s_load) where the
-// march loops run short of SGPRs, instead of spilling the ~70 SGPRs of constants
-// to VGPR lanes and reloading them with v_readlane, which are VALU instructions
-// (float-storage two-step loop: 1308 instead of 1479 VALU instructions per
-// three rows).
-__device__ __forceinline__ const KTConsts& kernarg_consts() {
-  auto kp = (const __attribute__((address_space(4))) KTConsts*)__builtin_amdgcn_kernarg_segment_ptr();
-  asm volatile("" : "+s"(kp));
-  return *(const KTConsts*)kp;
 }
 
 // REC: also store the intermediate state f1 to f1out (lb_run_record; arrays
@@ -1976,9 +1983,13 @@ struct Tile {
 // Default launch shape: 256 x 16 tiles on large grids; on smaller grids the
 // tile shrinks (rows first, down to 2, then columns) until there are at least
 // 1024 tiles, four per compute unit.
-static void default_tile(int nx, int ny, int* bx, int* rows, int min_tiles = 1024) {
+// Default launch shape of the one-step kernel: 256 x 32 tiles, 256 x 64 for
+// float storage (8192 x 2048 grid, ms per step in two interleaved rounds: float
+// 0.2519-0.2530 at 64 rows vs 0.2544 at 32), shrunk on smaller grids (rows, then
+// columns) until there are at least min_tiles tiles.
+static void default_tile(int nx, int ny, int* bx, int* rows, int min_tiles = 1024, int r0 = 32) {
   auto ntiles = [&](int b, int r) { return cdiv(nx, b) * cdiv(ny, r); };
-  int b = 256, r = 32;
+  int b = 256, r = r0;
   while (ntiles(b, r) < min_tiles && r > 2) r /= 2;
   while (ntiles(b, r) < min_tiles && b > 64) b /= 2;
   *bx = b;
@@ -2052,7 +2063,12 @@ static lb_status resolve_tile(const lb_tile* tile, int nx, int ny, Tile* t) {
 static lb_status launch_step(const lb_grid* g, const KTConsts& K, lb_prec prec, const void* fin, void* fout,
                              int64_t step, const Tile& t, hipStream_t st) {
   const bool w = wide(g, elem_size(prec));
-  const int bx = t.bx, rows = w ? std::min(t.rows, wide_max_rows(g, elem_size(prec))) : t.rows;
+  int bx = t.bx, rows = t.rows;
+  if (!t.user && prec == LB_F32) {
+    default_tile(g->nx, g->ny, &bx, &rows, 1024, 64);
+    rows = std::min(rows, g->ny);
+  }
+  if (w) rows = std::min(rows, wide_max_rows(g, elem_size(prec)));
   const int64_t ntiles64 = cdiv(g->nx, bx) * cdiv(g->ny, rows);
   if (ntiles64 > 0x7fffffff) return fail(LB_EINVAL, "grid too large for one launch");
   const int nstrips = (int)cdiv(g->nx, bx);
