@@ -1983,10 +1983,8 @@ struct Tile {
 // Default launch shape: 256 x 16 tiles on large grids; on smaller grids the
 // tile shrinks (rows first, down to 2, then columns) until there are at least
 // 1024 tiles, four per compute unit.
-// Default launch shape of the one-step kernel: 256 x 32 tiles, 256 x 64 for
-// float storage (8192 x 2048 grid, ms per step in two interleaved rounds: float
-// 0.2519-0.2530 at 64 rows vs 0.2544 at 32), shrunk on smaller grids (rows, then
-// columns) until there are at least min_tiles tiles.
+// Default launch shape of the one-step kernel: 256 x 32 tiles, shrunk on smaller
+// grids (rows, then columns) until there are at least min_tiles tiles.
 static void default_tile(int nx, int ny, int* bx, int* rows, int min_tiles = 1024, int r0 = 32) {
   auto ntiles = [&](int b, int r) { return cdiv(nx, b) * cdiv(ny, r); };
   int b = 256, r = r0;
@@ -1994,6 +1992,31 @@ static void default_tile(int nx, int ny, int* bx, int* rows, int min_tiles = 102
   while (ntiles(b, r) < min_tiles && b > 64) b /= 2;
   *bx = b;
   *rows = r;
+}
+
+// Default launch shape of the float one-step kernel, whose tiles run in XCD bands
+// (each XCD takes ntiles / 8 consecutive tiles of the raster): 256 columns by
+// about 52 rows, with the number of row chunks a multiple of 8, so that every
+// band is whole chunk rows. Measured on the 8192 x 2048 grid (ms per step, two
+// interleaved rounds): 52 rows (40 chunks) 0.2470-0.2480, 64 (32) 0.2521-0.2524,
+// 32 (64) 0.2537-0.2539, 43 (48) 0.2560, 128 (16) 0.2555, against 0.2585-0.2904 for
+// 46-60 rows whose bands end inside a chunk row. Grids where this leaves fewer
+// than 1024 tiles or tiles below 32 rows take 256 x 64 shrunk as above.
+static void default_tile1f(int nx, int ny, int* bx, int* rows) {
+  const int c0 = std::max(8, (int)std::lround(ny / (52.0 * 8.0)) * 8);
+  // chunk counts c0, c0 + 8, c0 - 8, ... (ny rows need not split into exactly c chunks)
+  for (int k = 0; k < 7; ++k) {
+    const int c = c0 + ((k + 1) / 2) * 8 * (k % 2 ? 1 : -1);
+    if (c < 8) continue;
+    const int r = cdiv(ny, c);
+    const int chunks = cdiv(ny, r);
+    if (r >= 32 && chunks % 8 == 0 && cdiv(nx, 256) * chunks >= 1024) {
+      *bx = 256;
+      *rows = r;
+      return;
+    }
+  }
+  default_tile(nx, ny, bx, rows, 1024, 64);
 }
 
 // Default launch shape of the two-step pass: 256 threads (4 x 60 columns) by
@@ -2065,7 +2088,7 @@ static lb_status launch_step(const lb_grid* g, const KTConsts& K, lb_prec prec, 
   const bool w = wide(g, elem_size(prec));
   int bx = t.bx, rows = t.rows;
   if (!t.user && prec == LB_F32) {
-    default_tile(g->nx, g->ny, &bx, &rows, 1024, 64);
+    default_tile1f(g->nx, g->ny, &bx, &rows);
     rows = std::min(rows, g->ny);
   }
   if (w) rows = std::min(rows, wide_max_rows(g, elem_size(prec)));
