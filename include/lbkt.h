@@ -119,7 +119,10 @@ typedef struct {
  * persistent blocks (rounded down to a multiple of 8 where tiles are dealt to
  * the XCDs in bands), each looping over tiles. All zero (or a NULL tile) = the
  * default: 256 x 32 tiles, one block per tile, shrunk on small grids (rows down
- * to 2, then columns) to give at least 1024 tiles; the two-step pass takes at
+ * to 2, then columns) to give at least 1024 tiles; one step per launch on a
+ * float array takes about 52 rows where the row chunks then number a multiple
+ * of 8 (each XCD's band of tiles is whole chunk rows) and there are at least
+ * 1024 tiles of at least 32 rows, else 64 rows shrunk alike; the two-step pass takes at
  * most 11 rows (double) or 23 rows (float) by default, the three-step pass 11
  * rows. In the two-step pass a wavefront of 64 threads produces 60 columns, in
  * the three-step pass 58, so a tile is block_x / 64 * 60 (58) columns wide. */
