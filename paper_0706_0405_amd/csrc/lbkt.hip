@@ -249,6 +249,10 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 #else
 #define LB_STEP_ATTR
 #endif
+// time steps per pass of lb_run on 4-row grids with a periodic y axis (4, 6 or 8)
+#ifndef LB_DEEP1
+#define LB_DEEP1 8
+#endif
 // waves per SIMD asked of the float one-step kernel below 4 GiB (its 168 VGPRs fit 3)
 #ifndef LB_STEP_F32_WAVES
 #define LB_STEP_F32_WAVES 3
@@ -1832,6 +1836,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     march_ny4_deep<D, false>(Ks + w.prob, fi, fo, L);
 }
 
+// D steps per pass over one 4-row grid with a periodic y axis (the pass lb_run
+// takes there): the march of the batched kernel above, one wavefront per block,
+// block b on the strip of columns starting at b * (64 - 2D); the grid constants
+// are the kernel argument K, read by the march through the kernel-argument
+// segment.
+template <typename S, int D>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_stepD_ny4(KTConsts K, const S* fin,
+                                                                                           S* fout) {
+  const KTConsts* Kp =
+      (const KTConsts*)(const __attribute__((address_space(4))) KTConsts*)__builtin_amdgcn_kernarg_segment_ptr();
+  const KTConsts& KM = consts_opaque(Kp);   // K itself
+  const int lane = threadIdx.x & 63;
+  const int X0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (64 - 2 * D));
+  if (X0 >= KM.nx) return;
+  constexpr int AUX = sizeof(S) == 8 ? 2 : 0;   // the stores of k_step2
+  const View<S, AUX, false> fi = make_view<S, AUX, false>(KM, fin), fo = make_view<S, AUX, false>(KM, fout);
+  const Lane2 L = make_lane2<S>(KM, X0, lane, D);
+  if (!L.perx && (X0 == 0 || X0 + 64 - D >= KM.nx))
+    march_ny4_deep<D, true>(Kp, fi, fo, L);
+  else
+    march_ny4_deep<D, false>(Kp, fi, fo, L);
+}
+
 // One two-step work item of a batch: the strip of block_x / 64 wavefronts (60
 // output columns each) of problem w.prob, all rows. NY4: every problem of the
 // batch has 4 rows and a periodic y axis (an instantiation of its own, so that the
@@ -2173,6 +2200,27 @@ static lb_status launch_step3(const lb_grid* g, const KTConsts& K, const void* f
   return LB_OK;
 }
 
+// The deep pass of lb_run (k_stepD_ny4, LB_DEEP1 steps with the strip's whole
+// state in registers) runs on 4-row grids with a periodic y axis, at least 64
+// columns and an array below 4 GiB.
+static bool deep1_ok(const lb_grid* g, lb_prec prec) {
+  return g->ny == 4 && g->edge[2].kind == LB_BC_PERIODIC && g->nx >= 64 && !wide(g, elem_size(prec));
+}
+
+static lb_status launch_stepD1(const lb_grid* g, const KTConsts& K, lb_prec prec, const void* fin, void* fout,
+                               hipStream_t st) {
+  constexpr int D = LB_DEEP1;
+  const int nblocks = (int)cdiv(g->nx, 64 - 2 * D);
+  if (prec == LB_F64)
+    hipLaunchKernelGGL((k_stepD_ny4<double, D>), dim3(nblocks), dim3(64), 0, st, K, (const double*)fin,
+                       (double*)fout);
+  else
+    hipLaunchKernelGGL((k_stepD_ny4<float, D>), dim3(nblocks), dim3(64), 0, st, K, (const float*)fin,
+                       (float*)fout);
+  HIP_CHECK(hipGetLastError());
+  return LB_OK;
+}
+
 // Time steps per pass of lb_run for a resolved tile: by default 3 for FP64
 // arrays where the three-step kernel runs and ny >= 32, else the tile's (1 or
 // 2); an explicit 3 where that kernel does not run is LB_EUNSUPPORTED. On fewer
@@ -2182,6 +2230,10 @@ static lb_status launch_step3(const lb_grid* g, const KTConsts& K, const void* f
 static lb_status pass_steps(const lb_grid* g, lb_prec prec, const Tile& t, int* steps) {
   if (t.steps == 3 && !three_ok(g, prec))
     return fail(LB_EUNSUPPORTED, "three steps per pass run on FP64 arrays below 4 GiB with ny >= 3");
+  if (t.steps_auto && deep1_ok(g, prec)) {
+    *steps = LB_DEEP1;
+    return LB_OK;
+  }
   *steps = (t.steps_auto && three_ok(g, prec) && g->ny >= 32) ? 3 : t.steps;
   return LB_OK;
 }
@@ -2196,6 +2248,20 @@ static lb_status launch_steps(const lb_grid* g, const KTConsts& K, lb_prec prec,
   int sp;
   lb_status s0 = pass_steps(g, prec, t, &sp);
   if (s0) return s0;
+  if (sp == LB_DEEP1) {
+    // an even number of deep passes (each swaps the buffers once for an even
+    // number of steps), the remaining steps first, two per pass
+    const int deep = (nsteps / LB_DEEP1) & ~1;
+    const int rem = nsteps - deep * LB_DEEP1;
+    Tile t2 = t;
+    t2.steps = 2;
+    t2.steps_auto = false;
+    lb_status s;
+    if ((s = launch_steps(g, K, prec, fa, fb, step0, rem, t2, st))) return s;
+    for (int j = 0, k = rem % 2; j < deep; ++j, ++k)
+      if ((s = launch_stepD1(g, K, prec, (k % 2 == 0) ? fa : fb, (k % 2 == 0) ? fb : fa, st))) return s;
+    return LB_OK;
+  }
   if (sp == 3) {
     const int triples = nsteps / 3;
     int64_t n = step0;
@@ -2329,7 +2395,7 @@ extern "C" lb_status lb_run(const lb_grid* g, int32_t prec_code, void* fa, void*
   int sp;
   if ((s = pass_steps(g, prec, t, &sp))) return s;
   const std::string key =
-      run_key(g, prec, fa, fb, step0, nsteps, t.bx, (t.rows * 1000003 + t.blocks) * 4 + sp, stream);
+      run_key(g, prec, fa, fb, step0, nsteps, t.bx, (t.rows * 1000003 + t.blocks) * 16 + sp, stream);
   std::lock_guard<std::mutex> lock(g_graph_mu);
   for (auto& e : g_graphs)
     if (e.key == key) return launch_exec(e.exec, e.done, st);
