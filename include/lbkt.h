@@ -123,8 +123,8 @@ typedef struct {
  * float array takes about 52 rows where the row chunks then number a multiple
  * of 8 (each XCD's band of tiles is whole chunk rows) and there are at least
  * 1024 tiles of at least 32 rows, else 64 rows shrunk alike; the two-step pass takes at
- * most 11 rows (double) or 23 rows (float) by default, the three-step pass 11
- * rows. In the two-step pass a wavefront of 64 threads produces 60 columns, in
+ * most 11 rows (double) or 23 rows (float) by default, the three-step pass
+ * 128 x 12 tiles. In the two-step pass a wavefront of 64 threads produces 60 columns, in
  * the three-step pass 58, so a tile is block_x / 64 * 60 (58) columns wide. */
 typedef struct {
   int32_t block_x, rows, blocks;

@@ -2067,12 +2067,15 @@ static void default_tile2(int nx, int ny, lb_prec prec, int* bx, int* rows) {
 
 void lbkt_default_tile2(int nx, int ny, lb_prec prec, int* bx, int* rows) { default_tile2(nx, ny, prec, bx, rows); }
 
-// Default launch shape of the three-step pass (FP64): 256 threads (4 x 58
-// columns) by 11 rows, the fastest measured on the 8192 x 2048 grid among
-// 128 / 256 threads and 11-32 rows; shrunk on smaller grids as the two-step shape.
+// Default launch shape of the three-step pass (FP64): 128 threads (2 x 58
+// columns) by 12 rows, the fastest measured on the 8192 x 2048 grid among 64 /
+// 128 / 256 threads and 6-32 rows (ms per step, four rounds on two devices:
+// 128 x 12 0.2051-0.2059, 256 x 11 0.2079-0.2084, 128 x 11 0.2083, 128 x 9
+// 0.2078, 256 x 12 0.2093, 128 x 13 0.2110, 128 x 16 0.2231); shrunk on smaller
+// grids as the two-step shape.
 static void default_tile3(int nx, int ny, int* bx, int* rows) {
   auto ntiles = [&](int b, int r) { return cdiv(cdiv(nx, 58), b / 64) * cdiv(ny, r); };
-  int b = 256, r = 11;
+  int b = 128, r = 12;
   while (ntiles(b, r) < 1024 && r > 2) r = std::max(2, r / 2);
   while (ntiles(b, r) < 1024 && b > 64) b /= 2;
   if (ntiles(b, r) < 1024) r = 1;
