@@ -253,6 +253,10 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 #ifndef LB_DEEP1
 #define LB_DEEP1 8
 #endif
+// that pass with a strip's four rows on four wavefronts (1) or on one (0)
+#ifndef LB_DEEP1_ROWS
+#define LB_DEEP1_ROWS 1
+#endif
 // waves per SIMD asked of the float one-step kernel below 4 GiB (its 168 VGPRs fit 3)
 #ifndef LB_STEP_F32_WAVES
 #define LB_STEP_F32_WAVES 3
@@ -1859,6 +1863,69 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     march_ny4_deep<D, false>(Kp, fi, fo, L);
 }
 
+// The same D steps with the rows of a strip on the four wavefronts of a block:
+// wavefront r holds row r of the strip's 64 columns and computes that row of
+// every step with the per-row update of the march above (so the result is
+// bitwise the same); the rows of each step reach the other wavefronts through
+// LDS, written to one of two buffers while the other is read, with one barrier
+// per step. A step then costs one row of arithmetic instead of four, which is
+// what bounds a small grid. Every wavefront of a block runs every step (the
+// block's strip and its x-edge case are uniform), so all of them reach each
+// barrier.
+template <int D, bool XEDGE, class V>
+__device__ __forceinline__ void march_ny4_rows(const KTConsts& K, const V& fi, const V& fo, const Lane2& L, int r,
+                                               Sto<V> (*xs)[4][9][64]) {
+  using S = Sto<V>;
+  S c[9];
+  fi.raw9(r, L.vbx, c);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) xs[0][r][i][threadIdx.x & 63] = c[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, rm = (r + 3) & 3, rp = (r + 1) & 3;
+  for (int s = 0; s < D - 1; ++s) {
+    const int b = s & 1;
+    S p[9], n[9], o[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      p[i] = xs[b][rm][i][lane];
+      n[i] = xs[b][rp][i][lane];
+    }
+    ny4_state_step_row<false, XEDGE>(K, fi, L, r, p, c, n, o);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      c[i] = o[i];
+      xs[b ^ 1][r][i][lane] = o[i];
+    }
+    __syncthreads();
+  }
+  S p[9], n[9], t[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    p[i] = xs[(D - 1) & 1][rm][i][lane];
+    n[i] = xs[(D - 1) & 1][rp][i][lane];
+  }
+  ny4_state_step_row<true, XEDGE>(K, fo, L, r, p, c, n, t);
+}
+
+template <typename S, int D>
+__global__ __launch_bounds__(256) void k_stepD_ny4_rows(KTConsts K, const S* fin, S* fout) {
+  __shared__ S xs[2][4][9][64];
+  const KTConsts* Kp =
+      (const KTConsts*)(const __attribute__((address_space(4))) KTConsts*)__builtin_amdgcn_kernarg_segment_ptr();
+  const KTConsts& KM = consts_opaque(Kp);   // K itself
+  const int lane = threadIdx.x & 63;
+  const int r = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int X0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (64 - 2 * D));
+  if (X0 >= KM.nx) return;   // the whole block
+  constexpr int AUX = sizeof(S) == 8 ? 2 : 0;   // the stores of k_step2
+  const View<S, AUX, false> fi = make_view<S, AUX, false>(KM, fin), fo = make_view<S, AUX, false>(KM, fout);
+  const Lane2 L = make_lane2<S>(KM, X0, lane, D);
+  if (!L.perx && (X0 == 0 || X0 + 64 - D >= KM.nx))
+    march_ny4_rows<D, true>(KM, fi, fo, L, r, xs);
+  else
+    march_ny4_rows<D, false>(KM, fi, fo, L, r, xs);
+}
+
 // One two-step work item of a batch: the strip of block_x / 64 wavefronts (60
 // output columns each) of problem w.prob, all rows. NY4: every problem of the
 // batch has 4 rows and a periodic y axis (an instantiation of its own, so that the
@@ -2214,12 +2281,20 @@ static lb_status launch_stepD1(const lb_grid* g, const KTConsts& K, lb_prec prec
                                hipStream_t st) {
   constexpr int D = LB_DEEP1;
   const int nblocks = (int)cdiv(g->nx, 64 - 2 * D);
-  if (prec == LB_F64)
+  if (LB_DEEP1_ROWS) {
+    if (prec == LB_F64)
+      hipLaunchKernelGGL((k_stepD_ny4_rows<double, D>), dim3(nblocks), dim3(256), 0, st, K, (const double*)fin,
+                         (double*)fout);
+    else
+      hipLaunchKernelGGL((k_stepD_ny4_rows<float, D>), dim3(nblocks), dim3(256), 0, st, K, (const float*)fin,
+                         (float*)fout);
+  } else if (prec == LB_F64) {
     hipLaunchKernelGGL((k_stepD_ny4<double, D>), dim3(nblocks), dim3(64), 0, st, K, (const double*)fin,
                        (double*)fout);
-  else
+  } else {
     hipLaunchKernelGGL((k_stepD_ny4<float, D>), dim3(nblocks), dim3(64), 0, st, K, (const float*)fin,
                        (float*)fout);
+  }
   HIP_CHECK(hipGetLastError());
   return LB_OK;
 }
