@@ -129,10 +129,10 @@ typedef struct {
 typedef struct {
   int32_t block_x, rows, blocks;
   int32_t steps;   /* lb_run only: time steps per pass over the array, 1, 2 or 3; 0 = the
-                      default: 3 for FP64 arrays below 4 GiB with ny >= 32; 8 on grids of
-                      4 rows with a periodic y axis, at least 64 columns and an array
-                      below 4 GiB (a strip's whole state stays in registers, one
-                      wavefront per 48 columns, as in lb_step_batched); else 2 (1 when
+                      default: 3 for FP64 arrays below 4 GiB with ny >= 32; 16 on grids
+                      of 4 rows with a periodic y axis, at least 64 columns and an array
+                      below 4 GiB (a strip of 32 columns per block of four wavefronts,
+                      one row each, its state kept on chip between the steps); else 2 (1 when
                       ny < 2). Several steps per pass keep the intermediate states in
                       registers (temporal blocking): 1/2 or 1/3 of the HBM traffic per
                       step, bitwise the result of single steps. An explicit 3 runs on
@@ -171,8 +171,8 @@ lb_status lb_step_tiled(const lb_grid* grid, int32_t prec, const void* f_in, voi
  * state (with several steps per pass, not necessarily that of step nsteps-1).
  * With two steps per pass: 0-3 single steps, then an even number of two-step
  * passes; with three: 0-2 single steps, then nsteps / 3 three-step passes; with
- * eight: the steps beyond an even number of eight-step passes as with two, then
- * those passes.
+ * sixteen: the steps beyond an even number of sixteen-step passes as with two,
+ * then those passes.
  * use_graph != 0 captures the launches in a HIP graph (cached: a repeated call with
  * the same arguments replays it). Every launch shape and steps setting gives
  * bitwise the same result. */

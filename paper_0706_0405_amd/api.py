@@ -149,7 +149,7 @@ def step(grid: Grid, f_in, f_out, n=0, prec="f64", tile=None):
 def run(grid: Grid, f_a, f_b, nsteps, n0=0, prec="f64", use_graph=False, tile=None, steps_per_pass=0):
     """nsteps ping-pong steps; returns the tensor holding the result (lb_run).
     steps_per_pass: 1 = one step per launch, 2 = two, 3 = three (FP64 arrays); 0 = the
-    library default (three on FP64 arrays below 4 GiB with ny >= 32, eight on 4-row grids
+    library default (three on FP64 arrays below 4 GiB with ny >= 32, sixteen on 4-row grids
     with a periodic y axis and at least 64 columns, else two)."""
     pr = _prec(prec)
     _check_f(grid, pr, f_a, "f_a")

@@ -249,9 +249,11 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 #else
 #define LB_STEP_ATTR
 #endif
-// time steps per pass of lb_run on 4-row grids with a periodic y axis (4, 6 or 8)
+// time steps per pass of lb_run on 4-row grids with a periodic y axis (even, 4-20;
+// us per step on the paper's 1D configurations, rows on four wavefronts: 8 steps
+// 1.07-1.33, 12 0.99-1.16, 16 0.94-1.15)
 #ifndef LB_DEEP1
-#define LB_DEEP1 8
+#define LB_DEEP1 16
 #endif
 // that pass with a strip's four rows on four wavefronts (1) or on one (0)
 #ifndef LB_DEEP1_ROWS
@@ -1793,6 +1795,9 @@ __device__ __forceinline__ const KTConsts& consts_opaque(const KTConsts* p) {
 template <int D, bool XEDGE, class V>
 __device__ __forceinline__ void march_ny4_deep(const KTConsts* Kp, const V& fi, const V& fo, const Lane2& L) {
   static_assert(D >= 4 && D % 2 == 0, "the deep 4-row march takes an even number of steps >= 4");
+  // only strips starting at column 0 form left x ghosts: the next strip's lanes
+  // (from column 64 - 3D) must stay inside the grid
+  static_assert(64 - 3 * D >= 0, "a deep pass takes at most 21 steps");
   using S = Sto<V>;
   S a0[9], a1[9], a2[9], a3[9], b0[9], b1[9], b2[9], b3[9];
   fi.raw9(0, L.vbx, a0);
@@ -1875,6 +1880,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 template <int D, bool XEDGE, class V>
 __device__ __forceinline__ void march_ny4_rows(const KTConsts& K, const V& fi, const V& fo, const Lane2& L, int r,
                                                Sto<V> (*xs)[4][9][64]) {
+  static_assert(D >= 2 && D % 2 == 0 && 64 - 3 * D >= 0, "as the march above: even, at most 21 steps");
   using S = Sto<V>;
   S c[9];
   fi.raw9(r, L.vbx, c);
@@ -2473,7 +2479,7 @@ extern "C" lb_status lb_run(const lb_grid* g, int32_t prec_code, void* fa, void*
   int sp;
   if ((s = pass_steps(g, prec, t, &sp))) return s;
   const std::string key =
-      run_key(g, prec, fa, fb, step0, nsteps, t.bx, (t.rows * 1000003 + t.blocks) * 16 + sp, stream);
+      run_key(g, prec, fa, fb, step0, nsteps, t.bx, (t.rows * 1000003 + t.blocks) * 64 + sp, stream);
   std::lock_guard<std::mutex> lock(g_graph_mu);
   for (auto& e : g_graphs)
     if (e.key == key) return launch_exec(e.exec, e.done, st);
