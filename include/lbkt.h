@@ -313,10 +313,12 @@ void lb_batch_destroy(lb_batch* b);
 
 /* Time each candidate launch shape for (grid, prec) with HIP events on `stream`
  * (reps launches each, captured in a HIP graph and timed as one replay when
- * stream != NULL, as lb_run with use_graph runs them), for one step per launch
- * and for two steps per pass, and return the fastest per time step in *best
- * (best->steps tells which; pass it to lb_run as is) and its time per step in
- * *best_ms; f_a/f_b are scratch state. Synchronises `stream`. */
+ * stream != NULL, as lb_run with use_graph runs them), for one step per launch,
+ * two and (where they run) three steps per pass, and on 4-row grids with a
+ * periodic y axis the sixteen-step pass, and return the fastest per time step in
+ * *best (best->steps tells which, 0 for the sixteen-step pass, which lb_run takes
+ * by default there; pass it to lb_run as is) and its time per step in *best_ms;
+ * f_a/f_b are scratch state. Synchronises `stream`. */
 lb_status lb_autotune(const lb_grid* grid, int32_t prec, void* f_a, void* f_b, int32_t reps,
                       lb_tile* best, float* best_ms, void* stream);
 

@@ -3215,6 +3215,46 @@ extern "C" lb_status lb_autotune(const lb_grid* g, int32_t prec_code, void* fa, 
   lb_tile bt = {256, 16, 0, 0};
   KTConsts K;
   build_consts(g, &K);
+  // ms per launch of `launch` (in, out) -> lb_status: a warm-up launch, then reps
+  // timed launches, on a stream captured in a graph and timed as one replay (as
+  // lb_run with use_graph runs them; on small grids the gaps between direct
+  // launches would dominate)
+  auto time_launches = [&](auto&& launch, float* ms) -> lb_status {
+    lb_status ls = launch(fa, fb);
+    if (ls) return ls;
+    if (st != nullptr) {
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(LB_EHIP, "stream capture");
+      for (int n = 0; n < reps && ls == LB_OK; ++n) ls = launch((n % 2 == 0) ? fb : fa, (n % 2 == 0) ? fa : fb);
+      const hipError_t ce = hipStreamEndCapture(st, &graph);
+      if (ls != LB_OK || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return ls != LB_OK ? ls : fail(LB_EHIP, "stream capture");
+      }
+      const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) return fail(LB_EHIP, "graph instantiate");
+      hipError_t le = hipGraphLaunch(exec, st);   // warm replay
+      if (le == hipSuccess) le = hipEventRecord(e0, st);
+      if (le == hipSuccess) le = hipGraphLaunch(exec, st);
+      if (le == hipSuccess) le = hipEventRecord(e1, st);
+      if (le == hipSuccess) le = hipEventSynchronize(e1);
+      (void)hipGraphExecDestroy(exec);
+      if (le != hipSuccess) return fail(LB_EHIP, "graph replay");
+    } else {
+      if (hipEventRecord(e0, st) != hipSuccess) return fail(LB_EHIP, "event record");
+      for (int n = 0; n < reps; ++n)
+        if ((ls = launch((n % 2 == 0) ? fb : fa, (n % 2 == 0) ? fa : fb))) return ls;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return fail(LB_EHIP, "event sync");
+    }
+    *ms = 0.f;
+    (void)hipEventElapsedTime(ms, e0, e1);
+    *ms /= (float)reps;
+    return LB_OK;
+  };
   // every kernel lb_run can use: one step per launch, two per pass (ny >= 2), and
   // three per pass (FP64 arrays below 4 GiB, ny >= 3)
   const int spmax = three_ok(g, prec) ? 3 : (g->ny >= 2 ? 2 : 1);
@@ -3230,53 +3270,9 @@ extern "C" lb_status lb_autotune(const lb_grid* g, int32_t prec_code, void* fa, 
                    : sp == 2 ? launch_step2(g, K, prec, in, out, 0, t, st)
                              : launch_step3(g, K, in, out, 0, t, st);
           };
-          // warm-up launch, then reps timed launches: on a stream, captured in a
-          // graph and timed as one replay (as lb_run with use_graph runs them;
-          // on small grids the gaps between direct launches would dominate)
-          if ((s = launch(fa, fb))) goto done;
-          if (st != nullptr) {
-            hipGraph_t graph = nullptr;
-            hipGraphExec_t exec = nullptr;
-            if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-              s = fail(LB_EHIP, "stream capture");
-              goto done;
-            }
-            lb_status ls = LB_OK;
-            for (int n = 0; n < reps && ls == LB_OK; ++n) ls = launch((n % 2 == 0) ? fb : fa, (n % 2 == 0) ? fa : fb);
-            const hipError_t ce = hipStreamEndCapture(st, &graph);
-            if (ls != LB_OK || ce != hipSuccess) {
-              if (graph) (void)hipGraphDestroy(graph);
-              s = ls != LB_OK ? ls : fail(LB_EHIP, "stream capture");
-              goto done;
-            }
-            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (ie != hipSuccess) {
-              s = fail(LB_EHIP, "graph instantiate");
-              goto done;
-            }
-            hipError_t le = hipGraphLaunch(exec, st);   // warm replay
-            if (le == hipSuccess) le = hipEventRecord(e0, st);
-            if (le == hipSuccess) le = hipGraphLaunch(exec, st);
-            if (le == hipSuccess) le = hipEventRecord(e1, st);
-            if (le == hipSuccess) le = hipEventSynchronize(e1);
-            (void)hipGraphExecDestroy(exec);
-            if (le != hipSuccess) {
-              s = fail(LB_EHIP, "graph replay");
-              goto done;
-            }
-          } else {
-            if (hipEventRecord(e0, st) != hipSuccess) { s = fail(LB_EHIP, "event record"); goto done; }
-            for (int n = 0; n < reps; ++n)
-              if ((s = launch((n % 2 == 0) ? fb : fa, (n % 2 == 0) ? fa : fb))) goto done;
-            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-              s = fail(LB_EHIP, "event sync");
-              goto done;
-            }
-          }
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          ms /= (float)(reps * sp);   // per time step
+          float ms;
+          if ((s = time_launches(launch, &ms))) goto done;
+          ms /= (float)sp;   // per time step
           if (ms < bestv) {
             bestv = ms;
             bt.block_x = bx;
@@ -3285,6 +3281,21 @@ extern "C" lb_status lb_autotune(const lb_grid* g, int32_t prec_code, void* fa, 
             bt.steps = sp;
           }
         }
+  // the deep pass of 4-row grids with a periodic y axis (lb_run's default there,
+  // whatever the tile): steps = 0 in the result selects it
+  if (deep1_ok(g, prec)) {
+    auto launch = [&](const void* in, void* out) { return launch_stepD1(g, K, prec, in, out, st); };
+    float ms;
+    if ((s = time_launches(launch, &ms))) goto done;
+    ms /= (float)LB_DEEP1;
+    if (ms < bestv) {
+      bestv = ms;
+      default_tile(g->nx, g->ny, &bt.block_x, &bt.rows);
+      bt.rows = std::min(bt.rows, g->ny);
+      bt.blocks = 0;
+      bt.steps = 0;
+    }
+  }
 done:
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

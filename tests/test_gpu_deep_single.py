@@ -1,7 +1,8 @@
 """lb_run's deep pass on 4-row grids with a periodic y axis against one step per launch.
 
 On such grids (the paper's one-dimensional Riemann problems) lb_run's default keeps
-the whole state of a strip in registers for several steps per pass. Every
+the state of a strip on chip (a row per wavefront, the rows exchanged through LDS)
+for several steps per pass. Every
 intermediate state is rounded to the storage type and its x ghosts are formed as a
 single step forms them, so the array must be bitwise the one that one step per
 launch gives: for every x-edge kind (split edges too), widths around the strips
@@ -114,3 +115,25 @@ def test_narrow_grids_keep_the_general_passes():
         cfg = _smooth_cfg(nx, 4, X_SETS["walls"] + Y)
         one, other = _pair(lb, cfg, 20, "f64")
         assert _same(one, other)
+
+
+def test_autotuner_offers_the_deep_pass(tmp_path, monkeypatch):
+    """lb_autotune times the sixteen-step pass on such grids too and returns it as
+    steps = 0 (lb_run's default there): about three times faster per step than one
+    or two steps per launch on the paper's 1000:1 grid; the tuned tile gives the
+    same bits."""
+    lb = _lb()
+    from paper_0706_0405_amd import tuning
+    monkeypatch.setattr(tuning, "CACHE", str(tmp_path / "tune.json"))
+    cfg = P.ratio1000()
+    g = lb.Grid.from_workload(cfg)
+    rho, ux, uy, p = [torch.tensor(np.ascontiguousarray(a), dtype=F64, device=DEV) for a in P.init_fields(cfg)]
+    f0 = lb.init(g, rho, ux, uy, p, prec="f64")
+    tile = tuning.tile_for(g, f0.clone(), lb.empty(g, "f64", DEV), prec="f64", reps=4)
+    say("tuned tile 1000:1", tile)
+    assert tile[3] == 0 and tile[0] in (64, 128, 256) and tile[1] >= 1
+    outs = []
+    for kw in ({"steps_per_pass": 1}, {"tile": tile}):
+        fa, fb = f0.clone(), lb.empty(g, "f64", DEV)
+        outs.append(lb.interior(g, lb.run(g, fa, fb, 70, prec="f64", use_graph=True, **kw)).clone())
+    assert _same(outs[0], outs[1])
