@@ -193,8 +193,9 @@ def bench_batched(dev, steps=2000, nprob=256):
     """cfg: 256 Riemann problems of uneven length, FP32 storage, one graph launch of
     `steps` steps (the library's default for 4-row y-periodic batches: four steps
     per pass, each strip's state in registers) vs the sum of single-problem lb_run
-    runs (two steps per pass); and the same batch in FP64 storage at its default
-    eight steps per pass against two."""
+    runs (its default on these grids: sixteen steps per pass) and vs the plain
+    single-problem step (one step per launch); and the same batch in FP64 storage
+    at its default eight steps per pass against two."""
     import torch
     import paper_0706_0405_amd as lb
     from workloads import problems as P
@@ -254,12 +255,21 @@ def bench_batched(dev, steps=2000, nprob=256):
         for k, g in enumerate(grids):
             _, _, _, _, fl = lb.moments(g, B.view(out, k), prec="f32")
             nonfinite += int(int(fl[1]) > 0)
-        # the same problems one at a time (lb_run, one launch per two-step pass)
+        # the same problems one at a time: lb_run's default, and one step per launch
         t_single = 0.0
+        t_one = 0.0
         for k, (c, g) in enumerate(zip(cfgs, grids) if not PROFILE else ()):
             rho, ux, uy, p = fields_to(dev, P.init_fields(c))
             f1 = lb.init(g, rho, ux, uy, p, prec="f32")
             f2 = lb.empty(g, "f32", dev)
+            f1_0 = f1.clone()
+            torch.cuda.synchronize()
+            e0.record(s)
+            lb.run(g, f1, f2, steps, prec="f32", steps_per_pass=1)
+            e1.record(s)
+            torch.cuda.synchronize()
+            t_one += e0.elapsed_time(e1)
+            f1.copy_(f1_0)
             torch.cuda.synchronize()
             e0.record(s)
             r = lb.run(g, f1, f2, steps, prec="f32")
@@ -299,6 +309,8 @@ def bench_batched(dev, steps=2000, nprob=256):
     return {"problems": nprob, "steps": steps, "sites": sites, "draws": info, "block_x": block_x,
             "batched_ms": t_batch, "batched_ms_replays": spread(times),
             "single_sum_ms": t_single, "speedup": t_single / t_batch if t_single else None,
+            "single_one_step_per_launch_sum_ms": t_one,
+            "speedup_vs_one_step_per_launch": t_one / t_batch if t_one else None,
             "batched_mlups": mlups, "steps_per_pass": 4,
             "mlups_vs_one_step_hbm_bound": mlups * 1e6 * BYTES_PER_SITE["f32"] / (HBM_PEAK_GBS * 1e9),
             "nonfinite_problems": nonfinite, "f64_storage": f64}
