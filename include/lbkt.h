@@ -273,9 +273,12 @@ lb_status lb_batch_layout(const lb_batch* b, int64_t* offsets, int64_t* pitches,
 /* Set the launch shape of the batched step: block_x threads per work item (a
  * work item covers all rows of a strip of its problem); steps: time steps per
  * pass, 0 = the default, 1, 2, or 4, 6, 8 for a batch whose problems all have 4
- * rows and a periodic y axis (the whole state of a strip then stays in registers
- * for all the steps of a pass, and a wavefront produces 64 - 2 * steps columns);
- * the default for such a batch is 4 in FP32 and 8 in FP64 storage, else 2 (1
+ * rows and a periodic y axis (the whole state of a strip then stays on chip for
+ * all the steps of a pass, and a strip of 64 lanes produces 64 - 2 * steps
+ * columns; in FP32 storage at block_x 64 a strip's four rows run on the four
+ * wavefronts of a 256-thread block, one row each, exchanged through LDS);
+ * the default for such a batch is 4 steps and width 64 in FP32 and 8 steps in FP64
+ * storage (width 256 unless set), else 2 (1
  * when a problem has ny < 2). blocks = 0: one launch per pass (the default). blocks > 0: all
  * two-step passes of a call in ONE launch of at most `blocks` co-resident
  * blocks (fewer if fewer fit on the device at once), each block taking its
