@@ -300,7 +300,8 @@ class Batch:
     def set_tile(self, block_x, steps_per_pass=0, persistent_blocks=0, polls=0):
         """Threads per work item (64, 128, 256) and time steps per pass (0 = default; 1, 2,
         or 4, 6, 8 for a batch of 4-row y-periodic problems, whose default is 4 in FP32 and 8 in
-        FP64 storage);
+        FP64 storage; in FP32 storage at width 64, that batch's default width, the deep passes
+        run a strip's four rows on the four wavefronts of a 256-thread block);
         persistent_blocks > 0: all two-step passes in one launch of at most that many
         co-resident blocks (polls: poll budget per wait, 0 = the library's default)."""
         check(lib().lb_batch_set_tile(self.h, ctypes.byref(LbTile(int(block_x), int(polls), int(persistent_blocks),
